@@ -1,0 +1,216 @@
+#!/usr/bin/env python
+"""Throughput of the batched multirotor step on one MI355X.
+
+Workload (default): 1,048,576 X-quads, command mode drawn per vehicle from
+{position, velocity, attitude}, dt = 0.01 s.  A bench step is one step of
+every vehicle (controller, allocation, clamping, integration).  The timed
+region runs K steps with the autotuned fused policy (k steps per launch,
+state in registers, replayed from a HIP graph); the same K steps are also
+timed as K plain per-step launches.  Inputs are resident in HBM before
+timing starts.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per vehicle-step: bytes of the per-step
+# kernel (state in and out, 4-float command, mode byte) and FP32 flops of one
+# step on the shared straight-line path (quad allocation).
+BYTES_PER_VSTEP = 52 + 52 + 16 + 1
+FLOPS_PER_VSTEP = 291
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 78.6          # non-packed FP32 FMA: 256 CU x 64 lanes x 2 x 2.4 GHz
+FP32_PEAK_PACKED_TFLOPS = 157.3  # with packed FP32 (not used by this build)
+PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, sync):
+    sync()
+    t0 = time.perf_counter()
+    fn()
+    sync()
+    return time.perf_counter() - t0
+
+
+def event_time(stream, fn):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def cpu_baseline(wl, n_sample, steps):
+    import torch
+    import oracle
+    import workloads
+    torch.set_num_threads(max(1, len(os.sched_getaffinity(0))))
+    sub = workloads.subset(wl, n_sample)
+    s0, mode, tgt = oracle.step.from_workload_arrays(sub.state0, sub.mode, sub.target)
+    fleet = oracle.Fleet.from_groups(sub.groups, sub.n, sub.vparams)
+    t0 = time.perf_counter()
+    oracle.step.rollout(s0, mode, tgt, fleet, sub.dt, sub.g, steps)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * steps / dt, "unit": "vehicle-steps/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"first {n_sample} vehicles of the workload x {steps} steps (FP64 torch on CPU)",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=1_048_576)
+    ap.add_argument("--probe-steps", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-step", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--exec", type=str, default="", help="fixed fused policy 'block,vpl,k,grid' (skips tuning)")
+    ap.add_argument("--cpu-sample", type=int, default=65_536)
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: vehicles are independent, so N GPUs would each run "
+              "their own shard of the batch with no communication; run it once per GPU.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2305_16510_amd.sim import Sim
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    K, W = args.steps, args.warmup
+    wl = workloads.c2_scale(n=args.n)
+    log(f"workload {wl.name}: n={wl.n}")
+    sim = Sim.from_workload(wl, autotune_scratch=True)
+    sync = torch.cuda.synchronize
+    if args.exec:
+        b, v, k, g = (int(x) for x in args.exec.split(","))
+        sim.set_exec(kind=1, block=b, vpl=v, k=k, grid=g, use_graph=1)
+        tuned = sim.get_exec()
+    else:
+        t0 = time.perf_counter()
+        tuned = sim.autotune(args.probe_steps)
+        log(f"autotuned {tuned} in {time.perf_counter() - t0:.1f}s")
+    k = tuned["k"]
+
+    # ---- fused, graph-replayed ------------------------------------------------
+    sim.prepare(K)
+    sim.prepare(W)
+    sim.raw_step(W)
+    sync()
+    t_evt = {}
+
+    def run_fused():
+        t_evt["fused"] = event_time(sim.stream, lambda: sim.raw_step(K))
+
+    t_fused = timed(run_fused, sync)
+    launches = math.ceil(K / k)
+    kern_fused = t_evt["fused"] / launches
+    value = wl.n * K / t_fused
+    log(f"fused: {t_fused * 1e3:.2f} ms for {K} steps -> {value:.3e} vehicle-steps/s; "
+        f"kernel avg {kern_fused * 1e6:.1f} us over {launches} launches")
+
+    # ---- plain per-step launches ----------------------------------------------
+    per_step = None
+    if not args.no_per_step:
+        best = None
+        for blk in (64, 128, 256, 512):
+            sim.set_exec(kind=0, block=blk, use_graph=0)
+            sim.raw_step(20)
+            t = timed(lambda: sim.raw_step(50), sync)
+            if best is None or t < best[0]:
+                best = (t, blk)
+        sim.set_exec(kind=0, block=best[1], use_graph=0)
+        sim.raw_step(W)
+        sync()
+
+        def run_plain():
+            for _ in range(K):
+                sim.raw_step(1)
+
+        def run_plain_evt():
+            t_evt["plain"] = event_time(sim.stream, run_plain)
+
+        t_plain = timed(run_plain_evt, sync)
+        kern_plain = t_evt["plain"] / K
+        gbs = BYTES_PER_VSTEP * wl.n / kern_plain / 1e9
+        per_step = {
+            "value": wl.n * K / t_plain, "ms_per_step": t_plain / K * 1e3, "block": best[1],
+            "kernel_avg_us": kern_plain * 1e6,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        }
+        log(f"per-step: {t_plain * 1e3:.2f} ms -> {per_step['value']:.3e} vehicle-steps/s, "
+            f"kernel {kern_plain * 1e6:.1f} us = {gbs:.0f} GB/s")
+
+    tflops = FLOPS_PER_VSTEP * wl.n * k / kern_fused / 1e12
+    out = {
+        "metric": "vehicle-steps/s at 1M quads (fused vs per-step), %HBM/VALU peak; adjoint s/step",
+        "value": value,
+        "unit": "vehicle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": t_fused / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1,048,576 X-quads, modes uniform over position/velocity/attitude, "
+                               "dt=0.01 s (seeded synthetic)", "n_vehicles": wl.n, "seq_len": 1,
+                   "global_batch": wl.n, "parallelism": "none (1 GPU)", "exec": tuned},
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
+                     "flops_per_vehicle_step": FLOPS_PER_VSTEP,
+                     "peak_packed_fp32": FP32_PEAK_PACKED_TFLOPS},
+        "per_step": per_step,
+        "fused_over_per_step": (value / per_step["value"]) if per_step else None,
+        "paper_context": {"value": PAPER_VSTEPS, "unit": "vehicle-steps/s",
+                          "hardware": "2x RTX 3090 (use of the second GPU not stated)",
+                          "workload": "2^17 robots, attitude/velocity commands (Sec. VI)"},
+    }
+
+    if not args.no_extras:
+        wp = workloads.paper_context()
+        sp = Sim.from_workload(wp)
+        sp.set_exec(**{kk: tuned[kk] for kk in ("kind", "block", "vpl", "k", "grid", "use_graph")})
+        sp.prepare(K)
+        sp.raw_step(K)
+        sync()
+        tp = timed(lambda: sp.raw_step(K), sync)
+        out["paper_shape"] = {"value": wp.n * K / tp, "n_vehicles": wp.n,
+                              "workload": "2^17 quads, constant attitude or velocity commands, dt=0.01"}
+        sp.close()
+        log(f"paper shape 2^17: {wp.n * K / tp:.3e} vehicle-steps/s")
+
+    sim.close()
+    del sim
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, args.cpu_steps)
+        log(f"oracle: {out['cpu_baseline']['value']:.3e} vehicle-steps/s on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * ag.h -- C ABI of the batched multirotor step on MI355X (gfx950).
+ *
+ * The operation behind every call is the per-vehicle step of the parallel
+ * SE(3) geometric controller of Kulkarni, Forgaard and Alexis, "Aerial Gym --
+ * Isaac Gym Simulator for Aerial Robots" (arXiv 2305.16510):
+ *   - controller, Sec. IV: attitude mode (Sec. IV-A, eqs. (1)-(5)), velocity
+ *     mode (Sec. IV-B, eqs. (6)-(9)), position mode (named in Sec. I), plus a
+ *     wrench pass-through test mode;
+ *   - allocation of (f, M) to clamped rotor thrusts (the paper applies f and M
+ *     directly; Sec. II motivates modelling the rotor reaction torque);
+ *   - rigid-body Newton-Euler dynamics with quaternion integration (the part
+ *     the paper hands to its physics engine, Sec. I and end of Sec. IV-B).
+ * Vehicles are independent (data parallel over the batch, Sec. III and VI).
+ *
+ * Conventions.  All device arrays are structure-of-arrays with a common
+ * leading dimension `ld` (elements, ld >= n): row r of an array with R rows
+ * starts at element r*ld.  Vehicle i's state is
+ *   state[r*ld + i], r = 0..12: x(3) [m], v(3) [m/s], q(4) = (w, x, y, z)
+ *   Hamilton unit quaternion body->inertial, Omega(3) [rad/s] in the body frame.
+ * The inertial frame is z-up, gravity is -g e3, rotor thrust acts along +b3.
+ * mode[i] (int8) selects the command held in target[r*ld + i], r = 0..3:
+ *   0 position : (x_d, y_d, z_d, psi_d)              in the inertial frame
+ *   1 velocity : (v_d x, y, z in the vehicle frame V, psidot_d)   (eqs. (6)-(9))
+ *   2 attitude : (phi_d, theta_d, psidot_d, f)                   (eqs. (1)-(5))
+ *   3 wrench   : (f, M_x, M_y, M_z) passed to allocation (test mode)
+ *   other      : zero wrench command
+ * vparams (optional) rows: m, J1, J2, J3, 10 gains
+ *   (kx_xy, kx_z, kv_xy, kv_z, kR_x, kR_y, kR_z, kW_x, kW_y, kW_z), arm, u_max.
+ *
+ * Ownership.  The caller owns every device buffer (state, mode, target,
+ * vparams, outputs, workspaces) and keeps them alive while the handle uses
+ * them.  The library never allocates device memory; it owns only host-side
+ * bookkeeping and HIP graph objects.  All work is enqueued on cfg.stream.
+ *
+ * Errors.  Arguments are checked synchronously (AG_E_INVALID).  Device and
+ * launch failures are sticky: the failing call and every later call on the
+ * handle return AG_E_HIP until ag_destroy; ag_last_error gives the text.
+ * Non-finite vehicles are not errors: they are flagged per vehicle.
+ * A handle is not thread safe.
+ */
+#ifndef AG_H
+#define AG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AG_STATE_DIM 13
+#define AG_TARGET_DIM 4
+#define AG_VPARAM_DIM 16
+#define AG_NGAINS 10
+#define AG_MAX_ROTORS 8
+#define AG_WRENCH_DIM 8
+#define AG_MAX_GROUPS 4096
+
+typedef struct ag_sim* ag_handle;
+
+typedef enum {
+    AG_OK = 0,
+    AG_E_INVALID = 1,     /* bad argument; nothing was enqueued */
+    AG_E_HIP = 2,         /* HIP runtime or launch failure (sticky) */
+    AG_E_NOMEM = 3,       /* a caller workspace is too small */
+    AG_E_STATE = 4,       /* call not valid in the handle's current state */
+    AG_E_UNSUPPORTED = 5  /* feature combination not implemented */
+} ag_status;
+
+enum { AG_MODE_POSITION = 0, AG_MODE_VELOCITY = 1, AG_MODE_ATTITUDE = 2, AG_MODE_WRENCH = 3 };
+
+/* Per-vehicle flag bits written to cfg.flags_out at the end of each ag_step. */
+enum { AG_FLAG_NONFINITE = 1, AG_FLAG_SATURATED = 2, AG_FLAG_RESET = 4 };
+
+/* A contiguous range of vehicles sharing a rotor layout and default
+ * parameters.  Rotor layout (n_rotors in {4, 6, 8}): rotors at angles
+ * pi/n + 2 pi i/n in the body x-y plane at `arm`, spin (-1)^i, yaw torque
+ * c_tau per newton of thrust; thrusts are clamped to [u_min, u_max]. */
+typedef struct {
+    int64_t first, count;
+    int32_t n_rotors;
+    float arm, c_tau, u_min, u_max;
+    float mass;
+    float inertia[3];
+    float gains[AG_NGAINS];
+} ag_group_desc;
+
+typedef struct {
+    int64_t n;              /* vehicles, 1 .. 2^31-1 */
+    int64_t ld;             /* leading dimension of every SoA array, >= n */
+    float dt;               /* step [s] */
+    float g;                /* gravity [m/s^2] */
+    uint64_t seed;          /* key of the counter-based reset generator */
+    int64_t index_base;     /* global index of vehicle 0 (reset counters), index_base + n <= 2^32 */
+    void* stream;           /* hipStream_t; graphs are used only on a non-null stream */
+    int32_t n_groups;       /* 1 .. AG_MAX_GROUPS, covering [0, n) in order */
+    const ag_group_desc* groups;   /* host array, copied by ag_create */
+    float* state;           /* device [13][ld], read and written by ag_step / ag_reset */
+    int8_t* mode;           /* device [ld] */
+    float* target;          /* device [4][ld]; ag_reset and automatic resets rewrite goals */
+    const float* vparams;   /* device [16][ld] or NULL (group defaults) */
+    float* wrench_out;      /* device [8][ld] or NULL: commanded f, M and applied f', M' of the last step */
+    float* rotor_out;       /* device [8][ld] or NULL: clamped rotor thrusts of the last step (zero-padded) */
+    uint8_t* flags_out;     /* device [ld] or NULL: AG_FLAG_* bits of the last ag_step call */
+    float reset_prob;       /* probability of the counter-based reset mask (per vehicle and step) */
+    int32_t auto_reset;     /* 1: ag_step resets masked vehicles before every step */
+    float reset_lo[3];      /* box of redrawn positions and goals [m] */
+    float reset_hi[3];
+    int32_t collect_stats;  /* 1: ag_step accumulates the ag_stats counters and final-state sums */
+    int32_t autotune_scratch;  /* 1: workspace holds scratch state so ag_autotune leaves results untouched */
+} ag_config;
+
+/* Execution policy of ag_step.  kind 0: one launch of the per-step kernel per
+ * step (plain launches, one vehicle per lane).  kind 1: fused kernel keeping
+ * state in registers for k steps per launch, vpl vehicles per lane, a grid-
+ * stride loop over tiles of block*vpl vehicles (grid 0 = one block per tile),
+ * replayed from a cached HIP graph when use_graph is 1 and the stream is not
+ * null.  Every policy gives bitwise identical states. */
+typedef struct {
+    int32_t kind, block, vpl, k, grid, use_graph;
+} ag_exec;
+
+/* Batch statistics since the last clear.  Counters: saturated rotor commands
+ * (rotor-steps with the raw command outside [u_min, u_max]), automatic
+ * resets, invalid mode codes seen by ag_set_targets, steps taken.  Final-
+ * state values describe the state after the last ag_step. */
+typedef struct {
+    int64_t steps;
+    int64_t n_saturated;
+    int64_t n_resets;
+    int64_t n_invalid_mode;
+    int64_t n_nonfinite;    /* vehicles with a non-finite state */
+    int64_t n_finite;
+    int64_t n_position;     /* finite position-mode vehicles */
+    double pos_err_sum;     /* sum of |x - x_d| over finite position-mode vehicles */
+    double omega_sum;       /* sum of |Omega| over finite vehicles */
+} ag_stats;
+
+/* Device workspace (bytes) that ag_create needs for this configuration. */
+ag_status ag_workspace_size(const ag_config* cfg, size_t* bytes);
+
+/* Validate cfg, build the per-group tables (rotor allocation matrix and its
+ * min-norm pseudo-inverse, inverse mass and inertia) in FP64 on the host,
+ * round them to FP32 and upload them into `workspace` (device, >= the size
+ * from ag_workspace_size, 256-byte aligned).  Enqueues on cfg->stream. */
+ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_bytes, ag_handle* out);
+
+/* Release the host-side handle and its graphs (device buffers stay with the caller). */
+ag_status ag_destroy(ag_handle h);
+
+/* New commands for vehicles [first, first+count): copies mode_src[i] and
+ * target_src[r*src_ld + i] (device pointers; NULL = keep the bound buffers'
+ * contents) into the bound buffers and checks the mode codes; invalid codes
+ * are counted in ag_stats.n_invalid_mode (such vehicles get a zero wrench). */
+ag_status ag_set_targets(ag_handle h, int64_t first, int64_t count, const int8_t* mode_src,
+                         const float* target_src, int64_t src_ld);
+
+/* Advance every vehicle by n_steps steps (controller, allocation, clamping,
+ * integration; with auto_reset, the counter-based reset before each step),
+ * asynchronously on the handle's stream, with the current execution policy. */
+ag_status ag_step(ag_handle h, int32_t n_steps);
+
+/* Build and cache the HIP graph that ag_step(h, n_steps) will replay under
+ * the current execution policy, without launching it (no-op when the policy
+ * launches directly). */
+ag_status ag_prepare(ag_handle h, int32_t n_steps);
+
+ag_status ag_set_exec(ag_handle h, const ag_exec* e);
+ag_status ag_get_exec(ag_handle h, ag_exec* e);
+
+/* Time candidate fused policies (block, vehicles per lane, k, grid) for
+ * probe_steps steps each and keep the fastest; synchronises the stream.  With
+ * autotune_scratch the probes write scratch buffers, so the state is
+ * untouched; without it the call returns AG_E_STATE. */
+ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen);
+
+/* Reset vehicles before global step `step`: the mask is mask_in (device
+ * uint8[n], nonzero = reset) or, if NULL, the counter-based mask for that
+ * step.  Reset vehicles get a redrawn state and (position mode) goal.
+ * Optionally writes mask_out (uint8[n]), the ascending indices of reset
+ * vehicles (indices_out, int32[n]) and their number (count_out, int32[1]). */
+ag_status ag_reset(ag_handle h, const uint8_t* mask_in, int64_t step, uint8_t* mask_out,
+                   int32_t* indices_out, int32_t* count_out);
+
+/* Synchronise and read the statistics (clear = 1 zeroes the counters). */
+ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear);
+
+/* Global step counter (number of steps taken; used by automatic resets). */
+ag_status ag_get_step(ag_handle h, int64_t* step);
+ag_status ag_set_step(ag_handle h, int64_t step);
+
+/* Differentiable rollout of the tracking loss
+ *   L = scale_n * sum_i sum_{t=1..T} ( |x_{i,t} - x_goal,i|^2 + w_omega |Omega_{i,t}|^2 )
+ * over post-step states, x_goal = the position-mode target, scale_n = 1/n.
+ * Starting state x0 (device [13][ld]; NULL = the bound state, which is not
+ * modified).  Requires position or wrench modes and per-vehicle vparams.
+ * Forward: per-vehicle loss (loss_out [n], without scale_n) and checkpoints
+ * of the state every ckpt_every steps in `ws`; final_state optional [13][ld].
+ * Adjoint: recomputes each checkpoint segment and sweeps it backwards,
+ * writing dL/dgains (dgains [10][ld]) and dL/dx0 (dx0 [13][ld]) multiplied by
+ * `seed_grad`; both calls must use the same arguments and workspace. */
+ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_every, size_t* bytes);
+ag_status ag_rollout_forward(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every,
+                             float w_omega, void* ws, size_t ws_bytes, float* loss_out,
+                             float* final_state);
+ag_status ag_rollout_adjoint(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every,
+                             float w_omega, float seed_grad, void* ws, size_t ws_bytes,
+                             float* dgains, float* dx0);
+
+/* Wait for the handle's stream; returns a sticky error if one occurred. */
+ag_status ag_sync(ag_handle h);
+const char* ag_last_error(ag_handle h);
+const char* ag_status_string(ag_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AG_H */

@@ -1,0 +1,798 @@
+// ag_api.hip -- host runtime behind the C ABI of include/ag.h.
+//
+// Owns only host-side bookkeeping: validated configuration, workspace
+// layout, the per-group tables (built in FP64, rounded to FP32 and copied
+// into the caller's workspace), the step counter mirror, cached HIP graphs
+// of fused rollouts and the autotuner.  Every device buffer belongs to the
+// caller.  No hipMalloc anywhere.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ag.h"
+#include "ag_internal.h"
+#include "ag_step.h"
+
+using namespace ag;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct WsLayout {
+    size_t gtab, goff, d_step, acc, slots, block_counts, mask, scratch, total;
+    long long nslots, nblocks;
+};
+
+WsLayout ws_layout(const ag_config* c) {
+    WsLayout L{};
+    size_t off = 0;
+    L.gtab = off; off = align_up(off + (size_t)c->n_groups * GSTRIDE * sizeof(float));
+    L.goff = off; off = align_up(off + (size_t)(c->n_groups + 1) * sizeof(int32_t));
+    L.d_step = off; off = align_up(off + sizeof(long long));
+    L.acc = off; off = align_up(off + sizeof(StatAcc));
+    L.nslots = (c->n + 63) / 64;
+    L.slots = off; off = align_up(off + (size_t)L.nslots * sizeof(StatSlot));
+    L.nblocks = (c->n + kResetBlock - 1) / kResetBlock;
+    L.block_counts = off; off = align_up(off + (size_t)L.nblocks * sizeof(int32_t));
+    L.mask = off; off = align_up(off + (size_t)c->n);
+    L.scratch = off;
+    if (c->autotune_scratch) off = align_up(off + (size_t)(AG_STATE_DIM + AG_TARGET_DIM) * c->ld * sizeof(float));
+    L.total = off;
+    return L;
+}
+
+struct ExecKey {
+    int kind, block, vpl, k, grid, use_graph;
+    bool operator==(const ExecKey& o) const {
+        return kind == o.kind && block == o.block && vpl == o.vpl && k == o.k && grid == o.grid &&
+               use_graph == o.use_graph;
+    }
+};
+
+struct GraphEntry {
+    int n_steps;
+    ExecKey key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    unsigned long long stamp;
+};
+
+}  // namespace
+
+struct ag_sim {
+    ag_config cfg;
+    std::vector<ag_group_desc> groups;
+    std::vector<int32_t> goff_host;
+    hipStream_t stream;
+    char* ws;
+    WsLayout L;
+    float* gtab;
+    int32_t* goff;
+    long long* d_step;
+    StatAcc* acc;
+    StatSlot* slots;
+    int32_t* block_counts;
+    uint8_t* mask_buf;
+    float* scratch;
+    int nr_class;
+    bool vp;
+    bool reset_on;
+    uint32_t key0, key1;
+    unsigned long long thr;
+    ag_exec exec;
+    long long t;
+    bool dev_step_dirty;
+    std::vector<GraphEntry> graphs;
+    unsigned long long stamp;
+    ag_status sticky;
+    std::string err;
+    int num_cus;
+    std::vector<std::pair<long long, int>> span_cache;
+};
+
+namespace {
+
+ag_status set_err(ag_handle h, ag_status s, const std::string& msg) {
+    if (h) {
+        h->err = msg;
+        if (s == AG_E_HIP) h->sticky = AG_E_HIP;
+    }
+    return s;
+}
+
+ag_status hip_fail(ag_handle h, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_err(h, AG_E_HIP, m);
+}
+
+#define AG_HIP(h, call)                                   \
+    do {                                                  \
+        hipError_t e__ = (call);                          \
+        if (e__ != hipSuccess) return hip_fail(h, e__, #call); \
+    } while (0)
+
+#define AG_CHECK_HANDLE(h)                                \
+    do {                                                  \
+        if (!(h)) return AG_E_INVALID;                    \
+        if ((h)->sticky != AG_OK) return (h)->sticky;     \
+    } while (0)
+
+// ---- FP64 group tables -------------------------------------------------------
+// Rotor layout: n rotors at pi/n + 2 pi i/n, spin (-1)^i.  Unit-arm allocation
+// columns (1, sin a, -cos a, s c_tau); pseudo-inverse A^T (A A^T)^{-1}.
+bool invert4(double m[4][4], double inv[4][4]) {
+    double a[4][8];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 8; ++j) a[i][j] = j < 4 ? m[i][j] : (j - 4 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 4; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (std::fabs(a[r][c]) > std::fabs(a[p][c])) p = r;
+        if (std::fabs(a[p][c]) < 1e-300) return false;
+        for (int j = 0; j < 8; ++j) std::swap(a[c][j], a[p][j]);
+        const double d = a[c][c];
+        for (int j = 0; j < 8; ++j) a[c][j] /= d;
+        for (int r = 0; r < 4; ++r) {
+            if (r == c) continue;
+            const double f = a[r][c];
+            for (int j = 0; j < 8; ++j) a[r][j] -= f * a[c][j];
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) inv[i][j] = a[i][j + 4];
+    return true;
+}
+
+bool build_group_entry(const ag_group_desc& g, float* e) {
+    const int n = g.n_rotors;
+    double A[4][8] = {};
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        const double al = pi / n + 2.0 * pi * i / n;
+        const double s = (i % 2 == 0) ? 1.0 : -1.0;
+        A[0][i] = 1.0;
+        A[1][i] = std::sin(al);
+        A[2][i] = -std::cos(al);
+        A[3][i] = s * (double)g.c_tau;
+    }
+    double G[4][4] = {}, Gi[4][4];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+            for (int i = 0; i < n; ++i) G[r][c] += A[r][i] * A[c][i];
+    if (!invert4(G, Gi)) return false;
+    for (int k = 0; k < GSTRIDE; ++k) e[k] = 0.0f;
+    for (int i = 0; i < n; ++i) {
+        for (int r = 0; r < 4; ++r) {
+            double p = 0.0;
+            for (int c = 0; c < 4; ++c) p += A[c][i] * Gi[c][r];
+            e[G_APINV + 4 * i + r] = (float)p;
+            e[G_ACOL + 4 * i + r] = (float)A[r][i];
+        }
+    }
+    e[G_UMIN] = g.u_min;
+    e[G_UMAX] = g.u_max;
+    e[G_ARM] = g.arm;
+    e[G_INV_ARM] = (float)(1.0 / (double)g.arm);
+    e[G_MASS] = g.mass;
+    e[G_INV_MASS] = (float)(1.0 / (double)g.mass);
+    for (int k = 0; k < 3; ++k) {
+        e[G_J + k] = g.inertia[k];
+        e[G_JINV + k] = (float)(1.0 / (double)g.inertia[k]);
+    }
+    for (int k = 0; k < AG_NGAINS; ++k) e[G_GAINS + k] = g.gains[k];
+    e[G_NR] = (float)n;
+    return true;
+}
+
+std::string validate(const ag_config* c) {
+    if (!c) return "cfg is null";
+    if (c->n < 1 || c->n > 2147483647LL) return "n must be in [1, 2^31-1]";
+    if (c->ld < c->n) return "ld must be >= n";
+    if (!(c->dt > 0.0f) || !std::isfinite(c->dt)) return "dt must be positive and finite";
+    if (!std::isfinite(c->g)) return "g must be finite";
+    if (c->index_base < 0 || c->index_base + c->n > 4294967296LL) return "index_base + n must be <= 2^32";
+    if (!c->state || !c->mode || !c->target) return "state, mode and target buffers are required";
+    if (c->n_groups < 1 || c->n_groups > AG_MAX_GROUPS || !c->groups) return "n_groups must be in [1, AG_MAX_GROUPS]";
+    long long expect = 0;
+    for (int g = 0; g < c->n_groups; ++g) {
+        const ag_group_desc& d = c->groups[g];
+        if (d.first != expect || d.count < 1) return "groups must be non-empty, contiguous and in order";
+        expect += d.count;
+        if (d.n_rotors != 4 && d.n_rotors != 6 && d.n_rotors != 8) return "n_rotors must be 4, 6 or 8";
+        if (!(d.arm > 0) || !(d.c_tau > 0) || !(d.mass > 0)) return "arm, c_tau and mass must be positive";
+        if (!(d.inertia[0] > 0) || !(d.inertia[1] > 0) || !(d.inertia[2] > 0)) return "inertia must be positive";
+        if (!(d.u_min <= d.u_max)) return "u_min must be <= u_max";
+    }
+    if (expect != c->n) return "groups must cover [0, n)";
+    if (!(c->reset_prob >= 0.0f && c->reset_prob <= 1.0f)) return "reset_prob must be in [0, 1]";
+    for (int k = 0; k < 3; ++k)
+        if (!(c->reset_lo[k] <= c->reset_hi[k])) return "reset_lo must be <= reset_hi";
+    return "";
+}
+
+// Largest number of groups that any tile of `tile` consecutive vehicles overlaps.
+int tile_span(ag_handle h, long long tile) {
+    for (auto& p : h->span_cache)
+        if (p.first == tile) return p.second;
+    const long long n = h->cfg.n;
+    const int G = h->cfg.n_groups;
+    int best = 1, g = 0;
+    for (long long base = 0; base < n; base += tile) {
+        const long long end = std::min(base + tile, n) - 1;
+        while (g + 1 < G && h->goff_host[g + 1] <= base) ++g;
+        int gh = g;
+        while (gh + 1 < G && h->goff_host[gh + 1] <= end) ++gh;
+        best = std::max(best, gh - g + 1);
+    }
+    h->span_cache.push_back({tile, best});
+    return best;
+}
+
+size_t lds_bytes(int span) { return (size_t)span * GSTRIDE * sizeof(float) + (size_t)(span + 1) * sizeof(int32_t); }
+
+StepArgs base_args(ag_handle h) {
+    StepArgs a{};
+    a.state = h->cfg.state;
+    a.mode = h->cfg.mode;
+    a.target = h->cfg.target;
+    a.vparams = h->cfg.vparams;
+    a.gtab = h->gtab;
+    a.goff = h->goff;
+    a.wrench_out = h->cfg.wrench_out;
+    a.rotor_out = h->cfg.rotor_out;
+    a.flags_out = h->cfg.flags_out;
+    a.slots = h->cfg.collect_stats ? h->slots : nullptr;
+    a.n = h->cfg.n;
+    a.ld = h->cfg.ld;
+    a.n_groups = h->cfg.n_groups;
+    a.dt = h->cfg.dt;
+    a.g = h->cfg.g;
+    a.key0 = h->key0;
+    a.key1 = h->key1;
+    a.thr = h->thr;
+    a.index_base = (uint32_t)h->cfg.index_base;
+    for (int k = 0; k < 3; ++k) {
+        a.lo[k] = h->cfg.reset_lo[k];
+        a.hi[k] = h->cfg.reset_hi[k];
+    }
+    return a;
+}
+
+struct LaunchShape {
+    const void* fn;
+    dim3 grid, block;
+    size_t shmem;
+    int span;
+};
+
+std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
+    if (e.kind != 0 && e.kind != 1) return "exec.kind must be 0 (per-step) or 1 (fused)";
+    if (e.block < 64 || e.block > 512 || e.block % 64) return "exec.block must be a multiple of 64 in [64, 512]";
+    const bool one = e.kind == 0;
+    const int vpl = one ? 1 : e.vpl;
+    if (vpl != 1 && vpl != 2) return "exec.vpl must be 1 or 2";
+    if (!one && e.k < 1) return "exec.k must be >= 1";
+    if (e.grid < 0) return "exec.grid must be >= 0";
+    const long long tile = (long long)e.block * vpl;
+    const int span = tile_span(h, tile);
+    if (span > kMaxSpanLds) return "vehicle groups too small for this tile size (too many groups per tile)";
+    const long long ntiles = (h->cfg.n + tile - 1) / tile;
+    long long grid = (one || e.grid == 0) ? ntiles : std::min<long long>(e.grid, ntiles);
+    if (grid > h->L.nslots) grid = h->L.nslots;
+    if (grid > 2147483647LL) return "grid too large";
+    s.fn = step_kernel(h->nr_class, h->vp, h->reset_on, vpl, one);
+    s.grid = dim3((unsigned)grid);
+    s.block = dim3((unsigned)e.block);
+    s.span = span;
+    s.shmem = lds_bytes(span);
+    return "";
+}
+
+ag_status launch(ag_handle h, const void* fn, dim3 grid, dim3 block, size_t shmem, void* args) {
+    void* params[] = {args};
+    AG_HIP(h, hipLaunchKernel(fn, grid, block, params, shmem, h->stream));
+    return AG_OK;
+}
+
+ag_status launch_fold(ag_handle h, int nslots, long long steps) {
+    FoldArgs f{h->slots, nslots, h->acc, steps, 1};
+    return launch(h, fold_kernel(), dim3(1), dim3(256), 0, &f);
+}
+
+// Direct (non-graph) launches of n steps with exec e on the given buffers.
+ag_status run_direct(ag_handle h, const ag_exec& e, int n_steps, StepArgs a, bool fold) {
+    LaunchShape s;
+    std::string m = shape_for(h, e, s);
+    if (!m.empty()) return set_err(h, AG_E_INVALID, m);
+    a.span = s.span;
+    a.d_step = nullptr;
+    const int k = e.kind == 0 ? 1 : e.k;
+    for (int done = 0, j = 0; done < n_steps; done += k, ++j) {
+        a.t0 = h->t + done;
+        a.k = std::min(k, n_steps - done);
+        a.flags_accumulate = done > 0;
+        ag_status st = launch(h, s.fn, s.grid, s.block, s.shmem, &a);
+        if (st != AG_OK) return st;
+    }
+    if (fold && a.slots) return launch_fold(h, (int)s.grid.x, n_steps);
+    return AG_OK;
+}
+
+ag_status add_node(ag_handle h, hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t* dep, const void* fn,
+                   dim3 grid, dim3 block, size_t shmem, void* args) {
+    hipKernelNodeParams p{};
+    void* params[] = {args};
+    p.func = const_cast<void*>(fn);
+    p.gridDim = grid;
+    p.blockDim = block;
+    p.sharedMemBytes = (unsigned)shmem;
+    p.kernelParams = params;
+    p.extra = nullptr;
+    AG_HIP(h, hipGraphAddKernelNode(node, g, dep, dep ? 1 : 0, &p));
+    return AG_OK;
+}
+
+ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
+    LaunchShape s;
+    std::string m = shape_for(h, h->exec, s);
+    if (!m.empty()) return set_err(h, AG_E_INVALID, m);
+    hipGraph_t g;
+    AG_HIP(h, hipGraphCreate(&g, 0));
+    StepArgs a = base_args(h);
+    a.span = s.span;
+    a.d_step = h->d_step;
+    const int k = h->exec.kind == 0 ? 1 : h->exec.k;
+    hipGraphNode_t prev = nullptr, node = nullptr;
+    for (int done = 0; done < n_steps; done += k) {
+        a.t_off = done;
+        a.k = std::min(k, n_steps - done);
+        a.flags_accumulate = done > 0;
+        ag_status st = add_node(h, g, &node, prev ? &prev : nullptr, s.fn, s.grid, s.block, s.shmem, &a);
+        if (st != AG_OK) { hipGraphDestroy(g); return st; }
+        prev = node;
+    }
+    if (a.slots) {
+        FoldArgs f{h->slots, (int)s.grid.x, h->acc, n_steps, 1};
+        ag_status st = add_node(h, g, &node, &prev, fold_kernel(), dim3(1), dim3(256), 0, &f);
+        if (st != AG_OK) { hipGraphDestroy(g); return st; }
+        prev = node;
+    }
+    CounterArgs c{h->d_step, n_steps};
+    ag_status st = add_node(h, g, &node, &prev, advance_kernel(), dim3(1), dim3(64), 0, &c);
+    if (st != AG_OK) { hipGraphDestroy(g); return st; }
+    hipGraphExec_t ex;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { hipGraphDestroy(g); return hip_fail(h, e, "hipGraphInstantiate"); }
+    ge.n_steps = n_steps;
+    ge.key = {h->exec.kind, h->exec.block, h->exec.vpl, h->exec.k, h->exec.grid, h->exec.use_graph};
+    ge.graph = g;
+    ge.exec = ex;
+    ge.stamp = ++h->stamp;
+    return AG_OK;
+}
+
+void drop_graphs(ag_handle h) {
+    for (auto& ge : h->graphs) {
+        hipGraphExecDestroy(ge.exec);
+        hipGraphDestroy(ge.graph);
+    }
+    h->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ag_status_string(ag_status s) {
+    switch (s) {
+        case AG_OK: return "ok";
+        case AG_E_INVALID: return "invalid argument";
+        case AG_E_HIP: return "HIP error";
+        case AG_E_NOMEM: return "workspace too small";
+        case AG_E_STATE: return "invalid state";
+        case AG_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown";
+}
+
+ag_status ag_workspace_size(const ag_config* cfg, size_t* bytes) {
+    if (!bytes) return AG_E_INVALID;
+    std::string m = validate(cfg);
+    if (!m.empty()) return AG_E_INVALID;
+    *bytes = ws_layout(cfg).total;
+    return AG_OK;
+}
+
+ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_bytes, ag_handle* out) {
+    if (!out) return AG_E_INVALID;
+    *out = nullptr;
+    std::string m = validate(cfg);
+    if (!m.empty()) {
+        std::fprintf(stderr, "ag_create: %s\n", m.c_str());
+        return AG_E_INVALID;
+    }
+    WsLayout L = ws_layout(cfg);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return AG_E_INVALID;
+    if (workspace_bytes < L.total) return AG_E_NOMEM;
+
+    ag_sim* h = new ag_sim();
+    h->cfg = *cfg;
+    h->groups.assign(cfg->groups, cfg->groups + cfg->n_groups);
+    h->cfg.groups = nullptr;
+    h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+    h->ws = static_cast<char*>(workspace);
+    h->L = L;
+    h->gtab = reinterpret_cast<float*>(h->ws + L.gtab);
+    h->goff = reinterpret_cast<int32_t*>(h->ws + L.goff);
+    h->d_step = reinterpret_cast<long long*>(h->ws + L.d_step);
+    h->acc = reinterpret_cast<StatAcc*>(h->ws + L.acc);
+    h->slots = reinterpret_cast<StatSlot*>(h->ws + L.slots);
+    h->block_counts = reinterpret_cast<int32_t*>(h->ws + L.block_counts);
+    h->mask_buf = reinterpret_cast<uint8_t*>(h->ws + L.mask);
+    h->scratch = cfg->autotune_scratch ? reinterpret_cast<float*>(h->ws + L.scratch) : nullptr;
+    int maxr = 4;
+    for (auto& g : h->groups) maxr = std::max(maxr, g.n_rotors);
+    bool uniform = true;
+    for (auto& g : h->groups) uniform = uniform && g.n_rotors == h->groups[0].n_rotors;
+    h->nr_class = uniform ? h->groups[0].n_rotors : 8;
+    (void)maxr;
+    h->vp = cfg->vparams != nullptr;
+    h->reset_on = cfg->auto_reset != 0 && cfg->reset_prob > 0.0f;
+    h->key0 = (uint32_t)(cfg->seed & 0xFFFFFFFFull);
+    h->key1 = (uint32_t)(cfg->seed >> 32);
+    const double thr = std::floor((double)cfg->reset_prob * 4294967296.0);
+    h->thr = (unsigned long long)std::min(std::max(thr, 0.0), 4294967296.0);
+    h->t = 0;
+    h->dev_step_dirty = true;
+    h->stamp = 0;
+    h->sticky = AG_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        h->num_cus = 256;
+    h->exec = {1, 256, 1, 16, 0, h->stream != nullptr ? 1 : 0};
+
+    std::vector<float> tab((size_t)cfg->n_groups * GSTRIDE);
+    h->goff_host.resize(cfg->n_groups + 1);
+    for (int g = 0; g < cfg->n_groups; ++g) {
+        if (!build_group_entry(h->groups[g], &tab[(size_t)g * GSTRIDE])) {
+            delete h;
+            return AG_E_INVALID;
+        }
+        h->goff_host[g] = (int32_t)h->groups[g].first;
+    }
+    h->goff_host[cfg->n_groups] = (int32_t)cfg->n;
+    StatAcc zero{};
+    hipError_t e = hipMemcpyAsync(h->gtab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->goff, h->goff_host.data(), h->goff_host.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->acc, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        CounterArgs c{h->d_step, 0};
+        void* p1[] = {&c};
+        e = hipLaunchKernel(set_step_kernel(), dim3(1), dim3(64), p1, 0, h->stream);
+    }
+    if (e == hipSuccess) {
+        ClearArgs ca{h->slots, (int)L.nslots};
+        void* p2[] = {&ca};
+        e = hipLaunchKernel(clear_slots_kernel(), dim3((unsigned)((L.nslots + 255) / 256)), dim3(256), p2, 0,
+                            h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "ag_create: %s\n", hipGetErrorString(e));
+        delete h;
+        return AG_E_HIP;
+    }
+    h->dev_step_dirty = false;
+    *out = h;
+    return AG_OK;
+}
+
+ag_status ag_destroy(ag_handle h) {
+    if (!h) return AG_E_INVALID;
+    drop_graphs(h);
+    delete h;
+    return AG_OK;
+}
+
+ag_status ag_set_targets(ag_handle h, int64_t first, int64_t count, const int8_t* mode_src,
+                         const float* target_src, int64_t src_ld) {
+    AG_CHECK_HANDLE(h);
+    if (first < 0 || count < 0 || first + count > h->cfg.n) return set_err(h, AG_E_INVALID, "range out of bounds");
+    if (target_src && src_ld < count) return set_err(h, AG_E_INVALID, "src_ld must be >= count");
+    if (count == 0) return AG_OK;
+    SetTargetsArgs a{h->cfg.mode, h->cfg.target, mode_src, target_src, h->cfg.ld, src_ld, first, count, h->acc};
+    return launch(h, set_targets_kernel(), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, &a);
+}
+
+ag_status ag_set_exec(ag_handle h, const ag_exec* e) {
+    AG_CHECK_HANDLE(h);
+    if (!e) return AG_E_INVALID;
+    LaunchShape s;
+    std::string m = shape_for(h, *e, s);
+    if (!m.empty()) return set_err(h, AG_E_INVALID, m);
+    if (e->use_graph && !h->stream) return set_err(h, AG_E_INVALID, "graphs need a non-null stream");
+    h->exec = *e;
+    return AG_OK;
+}
+
+ag_status ag_get_exec(ag_handle h, ag_exec* e) {
+    if (!h || !e) return AG_E_INVALID;
+    *e = h->exec;
+    return AG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Find or build the cached graph for n_steps under the current policy.
+ag_status cached_graph(ag_handle h, int n_steps, GraphEntry** out) {
+    const ag_exec& e = h->exec;
+    ExecKey key{e.kind, e.block, e.vpl, e.k, e.grid, e.use_graph};
+    for (auto& g : h->graphs)
+        if (g.n_steps == n_steps && g.key == key) {
+            g.stamp = ++h->stamp;
+            *out = &g;
+            return AG_OK;
+        }
+    GraphEntry ng;
+    ag_status st = build_graph(h, n_steps, ng);
+    if (st != AG_OK) return st;
+    if (h->graphs.size() >= 8) {
+        auto old = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                    [](const GraphEntry& a, const GraphEntry& b) { return a.stamp < b.stamp; });
+        hipGraphExecDestroy(old->exec);
+        hipGraphDestroy(old->graph);
+        h->graphs.erase(old);
+    }
+    h->graphs.push_back(ng);
+    *out = &h->graphs.back();
+    return AG_OK;
+}
+
+bool uses_graph(ag_handle h, int n_steps) {
+    const ag_exec& e = h->exec;
+    const int k = e.kind == 0 ? 1 : e.k;
+    return e.use_graph && h->stream && (n_steps + k - 1) / k >= 2;
+}
+
+}  // namespace
+
+extern "C" {
+
+ag_status ag_prepare(ag_handle h, int32_t n_steps) {
+    AG_CHECK_HANDLE(h);
+    if (n_steps < 0) return set_err(h, AG_E_INVALID, "n_steps must be >= 0");
+    if (n_steps == 0 || !uses_graph(h, n_steps)) return AG_OK;
+    GraphEntry* ge = nullptr;
+    return cached_graph(h, n_steps, &ge);
+}
+
+ag_status ag_step(ag_handle h, int32_t n_steps) {
+    AG_CHECK_HANDLE(h);
+    if (n_steps < 0) return set_err(h, AG_E_INVALID, "n_steps must be >= 0");
+    if (n_steps == 0) return AG_OK;
+    if (!uses_graph(h, n_steps)) {
+        ag_status st = run_direct(h, h->exec, n_steps, base_args(h), true);
+        if (st != AG_OK) return st;
+        h->t += n_steps;
+        h->dev_step_dirty = true;
+        return AG_OK;
+    }
+    GraphEntry* ge = nullptr;
+    ag_status st = cached_graph(h, n_steps, &ge);
+    if (st != AG_OK) return st;
+    if (h->dev_step_dirty) {
+        CounterArgs c{h->d_step, h->t};
+        st = launch(h, set_step_kernel(), dim3(1), dim3(64), 0, &c);
+        if (st != AG_OK) return st;
+        h->dev_step_dirty = false;
+    }
+    AG_HIP(h, hipGraphLaunch(ge->exec, h->stream));
+    h->t += n_steps;
+    return AG_OK;
+}
+
+ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
+    AG_CHECK_HANDLE(h);
+    if (!h->scratch) return set_err(h, AG_E_STATE, "autotune needs cfg.autotune_scratch = 1");
+    if (probe_steps < 1) return set_err(h, AG_E_INVALID, "probe_steps must be >= 1");
+    const long long ld = h->cfg.ld;
+    float* s_state = h->scratch;
+    float* s_target = h->scratch + (size_t)AG_STATE_DIM * ld;
+    StepArgs a = base_args(h);
+    a.state = s_state;
+    a.target = s_target;
+    a.wrench_out = nullptr;
+    a.rotor_out = nullptr;
+    a.flags_out = nullptr;
+    hipEvent_t e0, e1;
+    AG_HIP(h, hipEventCreate(&e0));
+    AG_HIP(h, hipEventCreate(&e1));
+    int occ_blocks_per_cu = 0;
+    const int blocks[] = {64, 128, 256, 512};
+    const int vpls[] = {1, 2};
+    const int ks[] = {4, 8, 16, 32, 64};
+    ag_exec best = h->exec;
+    float best_ms = 1e30f;
+    const long long saved_t = h->t;
+    for (int b : blocks)
+        for (int v : vpls)
+            for (int k : ks) {
+                if (k > probe_steps && k != 4) continue;
+                for (int gmode = 0; gmode < 2; ++gmode) {
+                    ag_exec cand{1, b, v, k, 0, h->exec.use_graph};
+                    LaunchShape s;
+                    if (!shape_for(h, cand, s).empty()) continue;
+                    if (gmode == 1) {
+                        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_blocks_per_cu, s.fn, b, s.shmem) !=
+                                hipSuccess || occ_blocks_per_cu < 1)
+                            continue;
+                        long long gp = (long long)h->num_cus * occ_blocks_per_cu;
+                        gp = (gp + 7) / 8 * 8;
+                        if (gp >= (long long)s.grid.x) continue;
+                        cand.grid = (int)gp;
+                    }
+                    float ms_min = 1e30f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        AG_HIP(h, hipMemcpy2DAsync(s_state, ld * sizeof(float), h->cfg.state, ld * sizeof(float),
+                                                   h->cfg.n * sizeof(float), AG_STATE_DIM, hipMemcpyDeviceToDevice,
+                                                   h->stream));
+                        AG_HIP(h, hipMemcpy2DAsync(s_target, ld * sizeof(float), h->cfg.target,
+                                                   ld * sizeof(float), h->cfg.n * sizeof(float), AG_TARGET_DIM,
+                                                   hipMemcpyDeviceToDevice, h->stream));
+                        AG_HIP(h, hipEventRecord(e0, h->stream));
+                        ag_status st = run_direct(h, cand, probe_steps, a, false);
+                        if (st != AG_OK) {
+                            hipEventDestroy(e0);
+                            hipEventDestroy(e1);
+                            return st;
+                        }
+                        AG_HIP(h, hipEventRecord(e1, h->stream));
+                        AG_HIP(h, hipEventSynchronize(e1));
+                        float ms = 0.0f;
+                        AG_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+                        if (rep > 0) ms_min = std::min(ms_min, ms);
+                    }
+                    if (ms_min < best_ms) {
+                        best_ms = ms_min;
+                        best = cand;
+                    }
+                }
+            }
+    h->t = saved_t;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ClearArgs ca{h->slots, (int)h->L.nslots};
+    ag_status st = launch(h, clear_slots_kernel(), dim3((unsigned)((h->L.nslots + 255) / 256)), dim3(256), 0, &ca);
+    if (st != AG_OK) return st;
+    AG_HIP(h, hipStreamSynchronize(h->stream));
+    h->exec = best;
+    if (chosen) *chosen = best;
+    return AG_OK;
+}
+
+ag_status ag_reset(ag_handle h, const uint8_t* mask_in, int64_t step, uint8_t* mask_out, int32_t* indices_out,
+                   int32_t* count_out) {
+    AG_CHECK_HANDLE(h);
+    if (step < 0) return set_err(h, AG_E_INVALID, "step must be >= 0");
+    ResetArgs a{};
+    a.state = h->cfg.state;
+    a.mode = h->cfg.mode;
+    a.target = h->cfg.target;
+    a.mask_in = mask_in;
+    const bool need_scan = indices_out || count_out;
+    a.mask_out = mask_out ? mask_out : (need_scan ? h->mask_buf : nullptr);
+    a.block_counts = need_scan ? h->block_counts : nullptr;
+    a.n = h->cfg.n;
+    a.ld = h->cfg.ld;
+    a.t = step;
+    a.key0 = h->key0;
+    a.key1 = h->key1;
+    a.thr = h->thr;
+    a.index_base = (uint32_t)h->cfg.index_base;
+    for (int k = 0; k < 3; ++k) {
+        a.lo[k] = h->cfg.reset_lo[k];
+        a.hi[k] = h->cfg.reset_hi[k];
+    }
+    const unsigned nb = (unsigned)h->L.nblocks;
+    ag_status st = launch(h, reset_mask_kernel(), dim3(nb), dim3(kResetBlock), 0, &a);
+    if (st != AG_OK || !need_scan) return st;
+    ScanArgs sa{h->block_counts, (int)nb, count_out};
+    st = launch(h, reset_scan_kernel(), dim3(1), dim3(1024), 0, &sa);
+    if (st != AG_OK || !indices_out) return st;
+    ScatterArgs ca{a.mask_out, h->block_counts, indices_out, h->cfg.n};
+    return launch(h, reset_scatter_kernel(), dim3(nb), dim3(kResetBlock), 0, &ca);
+}
+
+ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear) {
+    AG_CHECK_HANDLE(h);
+    if (!out) return AG_E_INVALID;
+    StatAcc acc{};
+    AG_HIP(h, hipMemcpyAsync(&acc, h->acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
+    AG_HIP(h, hipStreamSynchronize(h->stream));
+    out->steps = acc.steps;
+    out->n_saturated = acc.n_saturated;
+    out->n_resets = acc.n_resets;
+    out->n_invalid_mode = acc.n_invalid_mode;
+    out->n_nonfinite = acc.n_nonfinite;
+    out->n_finite = acc.n_finite;
+    out->n_position = acc.n_position;
+    out->pos_err_sum = acc.pos_err_sum;
+    out->omega_sum = acc.omega_sum;
+    if (clear) {
+        StatAcc z{};
+        z.n_nonfinite = acc.n_nonfinite;
+        z.n_finite = acc.n_finite;
+        z.n_position = acc.n_position;
+        z.pos_err_sum = acc.pos_err_sum;
+        z.omega_sum = acc.omega_sum;
+        AG_HIP(h, hipMemcpyAsync(h->acc, &z, sizeof(z), hipMemcpyHostToDevice, h->stream));
+        AG_HIP(h, hipStreamSynchronize(h->stream));
+    }
+    return AG_OK;
+}
+
+ag_status ag_get_step(ag_handle h, int64_t* step) {
+    if (!h || !step) return AG_E_INVALID;
+    *step = h->t;
+    return AG_OK;
+}
+
+ag_status ag_set_step(ag_handle h, int64_t step) {
+    AG_CHECK_HANDLE(h);
+    if (step < 0) return set_err(h, AG_E_INVALID, "step must be >= 0");
+    h->t = step;
+    h->dev_step_dirty = true;
+    return AG_OK;
+}
+
+ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_every, size_t* bytes) {
+    AG_CHECK_HANDLE(h);
+    if (!bytes || n_steps < 1 || ckpt_every < 1) return AG_E_INVALID;
+    const long long n = h->cfg.n;
+    const long long n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
+    size_t off = 0;
+    off = align_up(off + (size_t)n_ckpt * AG_STATE_DIM * n * sizeof(float));
+    off = align_up(off + (size_t)ckpt_every * AG_STATE_DIM * n * sizeof(float));
+    *bytes = off;
+    return AG_OK;
+}
+
+ag_status ag_rollout_forward(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega,
+                             void* ws, size_t ws_bytes, float* loss_out, float* final_state) {
+    AG_CHECK_HANDLE(h);
+    (void)x0; (void)n_steps; (void)ckpt_every; (void)w_omega; (void)ws; (void)ws_bytes; (void)loss_out;
+    (void)final_state;
+    return set_err(h, AG_E_UNSUPPORTED, "rollout not built yet");
+}
+
+ag_status ag_rollout_adjoint(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega,
+                             float seed_grad, void* ws, size_t ws_bytes, float* dgains, float* dx0) {
+    AG_CHECK_HANDLE(h);
+    (void)x0; (void)n_steps; (void)ckpt_every; (void)w_omega; (void)seed_grad; (void)ws; (void)ws_bytes;
+    (void)dgains; (void)dx0;
+    return set_err(h, AG_E_UNSUPPORTED, "rollout not built yet");
+}
+
+ag_status ag_sync(ag_handle h) {
+    if (!h) return AG_E_INVALID;
+    if (h->sticky != AG_OK) return h->sticky;
+    AG_HIP(h, hipStreamSynchronize(h->stream));
+    return AG_OK;
+}
+
+const char* ag_last_error(ag_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// ag_internal.h -- kernel argument blocks and kernel lookup shared by the
+// kernel translation unit and the host runtime (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ag {
+
+// Statistics slot written by one block of a step launch (64 bytes).
+struct StatSlot {
+    long long n_saturated;   // accumulated over launches until folded
+    long long n_resets;      // accumulated over launches until folded
+    long long n_nonfinite;   // final state of the launch
+    long long n_finite;
+    long long n_position;
+    double pos_err_sum;
+    double omega_sum;
+    double pad;
+};
+
+// Cumulative statistics kept on the device.
+struct StatAcc {
+    long long steps, n_saturated, n_resets, n_invalid_mode;
+    long long n_nonfinite, n_finite, n_position;
+    double pos_err_sum, omega_sum;
+};
+
+struct StepArgs {
+    float* state;              // [13][ld] (read and written in place)
+    const int8_t* mode;        // [ld]
+    float* target;             // [4][ld] (goals rewritten by resets)
+    const float* vparams;      // [16][ld] or null
+    const float* gtab;         // [n_groups][GSTRIDE]
+    const int32_t* goff;       // [n_groups + 1]
+    float* wrench_out;         // [8][ld] or null
+    float* rotor_out;          // [8][ld] or null
+    uint8_t* flags_out;        // [ld] or null
+    StatSlot* slots;           // [grid] or null
+    const long long* d_step;   // device step counter (graph launches) or null
+    long long t0;              // first global step when d_step is null
+    long long t_off;           // added to *d_step
+    long long n, ld;
+    int32_t n_groups;
+    int32_t span;              // max groups overlapping one tile (LDS entries)
+    int32_t k;                 // steps per launch
+    int32_t flags_accumulate;  // OR flags into flags_out instead of overwriting
+    float dt, g;
+    uint32_t key0, key1;       // reset generator key
+    unsigned long long thr;    // reset threshold (word < thr)
+    uint32_t index_base;
+    float lo[3], hi[3];
+};
+
+struct ResetArgs {
+    float* state;
+    const int8_t* mode;
+    float* target;
+    const uint8_t* mask_in;    // or null: counter-based mask
+    uint8_t* mask_out;         // [n]
+    int32_t* block_counts;     // [nblocks]
+    long long n, ld;
+    long long t;
+    uint32_t key0, key1;
+    unsigned long long thr;
+    uint32_t index_base;
+    float lo[3], hi[3];
+};
+
+struct RolloutArgs {
+    const float* x0;           // [13][ld]
+    const int8_t* mode;
+    const float* target;
+    const float* vparams;      // required
+    const float* gtab;
+    const int32_t* goff;
+    float* ckpt;               // [n_ckpt][13][n]
+    float* tape;               // [m][13][n]
+    float* loss_out;           // [n] or null
+    float* final_state;        // [13][ld] or null
+    float* dgains;             // [10][ld]
+    float* dx0;                // [13][ld]
+    long long n, ld;
+    int32_t n_groups, span;
+    int32_t T, m, n_ckpt;
+    float dt, g, w_omega, seed_grad;
+};
+
+constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
+
+// Kernel lookup (defined in ag_kernels.hip).  nr_class: 4, 6 or 8.
+const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step);
+const void* fold_kernel();
+const void* advance_kernel();
+const void* set_step_kernel();
+const void* set_targets_kernel();
+const void* reset_mask_kernel();
+const void* reset_scan_kernel();
+const void* reset_scatter_kernel();
+const void* clear_slots_kernel();
+const void* rollout_fwd_kernel(int nr_class);
+const void* rollout_adj_kernel(int nr_class);
+
+struct FoldArgs {
+    StatSlot* slots;
+    int32_t nslots;
+    StatAcc* acc;
+    long long steps;
+    int32_t has_final;
+};
+
+struct SetTargetsArgs {
+    int8_t* mode_dst;
+    float* target_dst;
+    const int8_t* mode_src;
+    const float* target_src;
+    long long ld, src_ld, first, count;
+    StatAcc* acc;
+};
+
+struct ScanArgs {
+    int32_t* block_counts;     // in: counts, out: exclusive offsets
+    int32_t nblocks;
+    int32_t* count_out;        // or null
+};
+
+struct ScatterArgs {
+    const uint8_t* mask;
+    const int32_t* offsets;
+    int32_t* indices;
+    long long n;
+};
+
+struct CounterArgs {
+    long long* d_step;
+    long long value;
+};
+
+struct ClearArgs {
+    StatSlot* slots;
+    int32_t nslots;
+};
+
+constexpr int kResetBlock = 256;
+
+}  // namespace ag

@@ -1,0 +1,395 @@
+// ag_kernels.hip -- HIP kernels of the batched multirotor step for gfx950.
+//
+// Layout.  State, targets, parameters and outputs are structure-of-arrays
+// rows of length ld, so lane i of a wavefront touches element i of each row:
+// every load and store is a fully coalesced 256-byte wavefront access.  Each
+// block stages the table entries of the vehicle groups its tile overlaps in
+// LDS (rotor allocation matrix and pseudo-inverse, inverses of mass and
+// inertia, default gains); lanes find their group by scanning the staged
+// group offsets.
+//
+// k_step<NR, VP, RESET, VPL, ONE> is both the per-step kernel (ONE: one step
+// per launch, one tile per block) and the fused kernel (k steps per launch
+// with the state held in registers, VPL vehicles per lane, grid-stride loop
+// over tiles).  A grid that is a multiple of 8 keeps each tile on the same
+// XCD (and so the same L2) from launch to launch.  Both forms run the same
+// device function per step, so their results are bitwise identical.
+#include <hip/hip_runtime.h>
+
+#include "ag.h"
+#include "ag_internal.h"
+#include "ag_step.h"
+
+namespace ag {
+
+__device__ __forceinline__ int find_group(const int32_t* __restrict__ goff, int n_groups, long long i) {
+    int lo = 0, hi = n_groups;              // goff[lo] <= i < goff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)goff[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Stage the group entries overlapping vehicles [base, end) into LDS.
+__device__ __forceinline__ void stage_groups(float* lds, int* loff, int* sh, const float* __restrict__ gtab,
+                                             const int32_t* __restrict__ goff, int n_groups,
+                                             long long base, long long end) {
+    if (threadIdx.x == 0) {
+        const int glo = n_groups == 1 ? 0 : find_group(goff, n_groups, base);
+        const int ghi = n_groups == 1 ? 0 : find_group(goff, n_groups, end - 1);
+        sh[0] = glo;
+        sh[1] = ghi - glo + 1;
+    }
+    __syncthreads();
+    const int glo = sh[0], cnt = sh[1];
+    for (int e = threadIdx.x; e < cnt * GSTRIDE; e += blockDim.x) lds[e] = gtab[(long long)glo * GSTRIDE + e];
+    for (int e = threadIdx.x; e <= cnt; e += blockDim.x) loff[e] = goff[glo + e];
+    __syncthreads();
+}
+
+__device__ __forceinline__ const float* lane_group(const float* lds, const int* loff, int cnt, long long i) {
+    int j = 0;
+    while (j + 1 < cnt && i >= (long long)loff[j + 1]) ++j;
+    return lds + j * GSTRIDE;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block reduction of the per-lane statistics into one slot.
+__device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, long long c_nonf,
+                            long long c_fin, long long c_pos, double s_err, double s_w) {
+    __shared__ long long red_i[16][5];
+    __shared__ double red_d[16][2];
+    c_sat = wave_sum(c_sat); c_res = wave_sum(c_res); c_nonf = wave_sum(c_nonf);
+    c_fin = wave_sum(c_fin); c_pos = wave_sum(c_pos);
+    s_err = wave_sum(s_err); s_w = wave_sum(s_w);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red_i[wid][0] = c_sat; red_i[wid][1] = c_res; red_i[wid][2] = c_nonf;
+        red_i[wid][3] = c_fin; red_i[wid][4] = c_pos;
+        red_d[wid][0] = s_err; red_d[wid][1] = s_w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        long long a[5] = {0, 0, 0, 0, 0};
+        double d[2] = {0.0, 0.0};
+        for (int w = 0; w < nw; ++w) {
+            for (int k = 0; k < 5; ++k) a[k] += red_i[w][k];
+            d[0] += red_d[w][0];
+            d[1] += red_d[w][1];
+        }
+        StatSlot* s = slots + blockIdx.x;
+        s->n_saturated += a[0];
+        s->n_resets += a[1];
+        s->n_nonfinite = a[2];
+        s->n_finite = a[3];
+        s->n_position = a[4];
+        s->pos_err_sum = d[0];
+        s->omega_sum = d[1];
+    }
+}
+
+template <int NR, bool VP, bool RESET, int VPL, bool ONE>
+__global__ __launch_bounds__(512) void k_step(StepArgs a) {
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
+    __shared__ int sh[2];
+
+    const int B = blockDim.x;
+    const long long TILE = (long long)B * VPL;
+    const long long ntiles = (a.n + TILE - 1) / TILE;
+    const long long tbase = a.d_step ? (*a.d_step + a.t_off) : a.t0;
+    const int K = ONE ? 1 : a.k;
+    const long long ld = a.ld;
+    const bool want_out = a.wrench_out != nullptr || a.rotor_out != nullptr;
+
+    long long c_sat = 0, c_res = 0, c_nonf = 0, c_fin = 0, c_pos = 0;
+    double s_err = 0.0, s_w = 0.0;
+
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long long base = tile * TILE;
+        const long long end = base + TILE < a.n ? base + TILE : a.n;
+        stage_groups(lds, loff, sh, a.gtab, a.goff, a.n_groups, base, end);
+        const int cnt = sh[1];
+
+        float s[VPL][13];
+        Cmd C[VPL];
+        Params P[VPL];
+        const float* gt[VPL];
+        long long idx[VPL];
+        bool act[VPL];
+        int sat_last[VPL];
+        bool did_reset[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            const long long i = base + (long long)v * B + threadIdx.x;
+            idx[v] = i;
+            act[v] = i < a.n;
+            sat_last[v] = 0;
+            did_reset[v] = false;
+            if (act[v]) {
+#pragma unroll
+                for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + i];
+                gt[v] = lane_group(lds, loff, cnt, i);
+                load_params<VP>(P[v], gt[v], a.vparams, ld, i);
+                derive_cmd(C[v], (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i],
+                           a.target[3 * ld + i]);
+            }
+        }
+
+        Wrench W[VPL];
+        float u[VPL][NR];
+        for (int st = 0; st < K; ++st) {
+            const bool out_step = want_out && st == K - 1;
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                if (!act[v]) continue;
+                if constexpr (RESET) {
+                    const uint32_t gi = a.index_base + (uint32_t)idx[v];
+                    if (reset_mask(gi, tbase + st, a.key0, a.key1, a.thr)) {
+                        float gx, gy, gz;
+                        redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
+                        if (C[v].mode == 0) derive_cmd(C[v], 0, gx, gy, gz, 0.0f);
+                        did_reset[v] = true;
+                        ++c_res;
+                    }
+                }
+                int ns;
+                if (out_step) ns = step<NR, true, true>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
+                else ns = step<NR, false, false>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
+                c_sat += ns;
+                sat_last[v] = ns;
+            }
+        }
+
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            if (!act[v]) continue;
+            const long long i = idx[v];
+#pragma unroll
+            for (int r = 0; r < 13; ++r) a.state[r * ld + i] = s[v][r];
+            if constexpr (RESET) {
+                if (did_reset[v] && C[v].mode == 0) {
+                    a.target[i] = C[v].t0;
+                    a.target[ld + i] = C[v].t1;
+                    a.target[2 * ld + i] = C[v].t2;
+                    a.target[3 * ld + i] = C[v].t3;
+                }
+            }
+            if (want_out) {
+                if (a.wrench_out) {
+                    a.wrench_out[i] = W[v].f;
+                    a.wrench_out[ld + i] = W[v].M0;
+                    a.wrench_out[2 * ld + i] = W[v].M1;
+                    a.wrench_out[3 * ld + i] = W[v].M2;
+                    a.wrench_out[4 * ld + i] = W[v].fa;
+                    a.wrench_out[5 * ld + i] = W[v].Ma0;
+                    a.wrench_out[6 * ld + i] = W[v].Ma1;
+                    a.wrench_out[7 * ld + i] = W[v].Ma2;
+                }
+                if (a.rotor_out) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) a.rotor_out[r * ld + i] = r < NR ? u[v][r] : 0.0f;
+                }
+            }
+            bool finite = true;
+#pragma unroll
+            for (int r = 0; r < 13; ++r) finite = finite && isfinite(s[v][r]);
+            if (a.flags_out) {
+                uint8_t fl = (finite ? 0 : AG_FLAG_NONFINITE) | (sat_last[v] ? AG_FLAG_SATURATED : 0) |
+                             (did_reset[v] ? AG_FLAG_RESET : 0);
+                if (a.flags_accumulate) fl |= (a.flags_out[i] & AG_FLAG_RESET);
+                a.flags_out[i] = fl;
+            }
+            if (a.slots) {
+                if (finite) {
+                    ++c_fin;
+                    s_w += (double)sqrtf(s[v][10] * s[v][10] + s[v][11] * s[v][11] + s[v][12] * s[v][12]);
+                    if (C[v].mode == 0) {
+                        ++c_pos;
+                        const float ex = s[v][0] - C[v].t0, ey = s[v][1] - C[v].t1, ez = s[v][2] - C[v].t2;
+                        s_err += (double)sqrtf(ex * ex + ey * ey + ez * ez);
+                    }
+                } else {
+                    ++c_nonf;
+                }
+            }
+        }
+        __syncthreads();   // LDS is restaged for the next tile
+    }
+    if (a.slots) block_stats(a.slots, c_sat, c_res, c_nonf, c_fin, c_pos, s_err, s_w);
+}
+
+// ---- statistics fold: slots -> cumulative accumulator (one block) ---------
+__global__ __launch_bounds__(256) void k_fold(FoldArgs a) {
+    __shared__ long long ri[256][5];
+    __shared__ double rd[256][2];
+    long long c[5] = {0, 0, 0, 0, 0};
+    double d[2] = {0.0, 0.0};
+    for (int s = threadIdx.x; s < a.nslots; s += 256) {
+        StatSlot* p = a.slots + s;
+        c[0] += p->n_saturated; c[1] += p->n_resets; c[2] += p->n_nonfinite;
+        c[3] += p->n_finite; c[4] += p->n_position;
+        d[0] += p->pos_err_sum; d[1] += p->omega_sum;
+        p->n_saturated = 0;
+        p->n_resets = 0;
+    }
+    for (int k = 0; k < 5; ++k) ri[threadIdx.x][k] = c[k];
+    rd[threadIdx.x][0] = d[0];
+    rd[threadIdx.x][1] = d[1];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 5; ++k) ri[threadIdx.x][k] += ri[threadIdx.x + w][k];
+            rd[threadIdx.x][0] += rd[threadIdx.x + w][0];
+            rd[threadIdx.x][1] += rd[threadIdx.x + w][1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.acc->steps += a.steps;
+        a.acc->n_saturated += ri[0][0];
+        a.acc->n_resets += ri[0][1];
+        if (a.has_final) {
+            a.acc->n_nonfinite = ri[0][2];
+            a.acc->n_finite = ri[0][3];
+            a.acc->n_position = ri[0][4];
+            a.acc->pos_err_sum = rd[0][0];
+            a.acc->omega_sum = rd[0][1];
+        }
+    }
+}
+
+__global__ void k_clear_slots(ClearArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < a.nslots) {
+        StatSlot z = {0, 0, 0, 0, 0, 0.0, 0.0, 0.0};
+        a.slots[s] = z;
+    }
+}
+
+__global__ void k_advance(CounterArgs a) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *a.d_step += a.value;
+}
+
+__global__ void k_set_step(CounterArgs a) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *a.d_step = a.value;
+}
+
+__global__ __launch_bounds__(256) void k_set_targets(SetTargetsArgs a) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.count) return;
+    const long long i = a.first + j;
+    if (a.mode_src) a.mode_dst[i] = a.mode_src[j];
+    if (a.target_src) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a.target_dst[r * a.ld + i] = a.target_src[r * a.src_ld + j];
+    }
+    const int m = (int)a.mode_dst[i];
+    if (m < 0 || m > 3) atomicAdd(reinterpret_cast<unsigned long long*>(&a.acc->n_invalid_mode), 1ull);
+}
+
+// ---- explicit reset: mask, redraw, per-block counts ------------------------
+__global__ __launch_bounds__(kResetBlock) void k_reset_mask(ResetArgs a) {
+    const long long i = (long long)blockIdx.x * kResetBlock + threadIdx.x;
+    bool m = false;
+    if (i < a.n) {
+        const uint32_t gi = a.index_base + (uint32_t)i;
+        m = a.mask_in ? (a.mask_in[i] != 0) : reset_mask(gi, a.t, a.key0, a.key1, a.thr);
+        if (m) {
+            float s[13], gx, gy, gz;
+            redraw(s, gx, gy, gz, gi, a.t, a.key0, a.key1, a.lo, a.hi);
+#pragma unroll
+            for (int r = 0; r < 13; ++r) a.state[r * a.ld + i] = s[r];
+            if (a.mode[i] == 0) {
+                a.target[i] = gx;
+                a.target[a.ld + i] = gy;
+                a.target[2 * a.ld + i] = gz;
+                a.target[3 * a.ld + i] = 0.0f;
+            }
+        }
+        if (a.mask_out) a.mask_out[i] = m ? 1 : 0;
+    }
+    const int c = __syncthreads_count(m);
+    if (threadIdx.x == 0 && a.block_counts) a.block_counts[blockIdx.x] = c;
+}
+
+// Exclusive scan of the block counts in place (one block, fixed order).
+__global__ __launch_bounds__(1024) void k_reset_scan(ScanArgs a) {
+    __shared__ int buf[1024];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < a.nblocks; base += 1024) {
+        const int j = base + threadIdx.x;
+        const int v = j < a.nblocks ? a.block_counts[j] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int t = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (j < a.nblocks) a.block_counts[j] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && a.count_out) *a.count_out = carry;
+}
+
+__global__ __launch_bounds__(kResetBlock) void k_reset_scatter(ScatterArgs a) {
+    __shared__ int wave_cnt[kResetBlock / 64];
+    const long long i = (long long)blockIdx.x * kResetBlock + threadIdx.x;
+    const bool m = i < a.n && a.mask[i] != 0;
+    const unsigned long long bal = __ballot(m);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int rank_in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_cnt[wid] = __popcll(bal);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wid; ++w) before += wave_cnt[w];
+    if (m) a.indices[a.offsets[blockIdx.x] + before + rank_in_wave] = (int32_t)i;
+}
+
+// ---- kernel lookup ---------------------------------------------------------
+template <int NR, bool VP, bool RESET>
+static const void* pick_step(int vpl, bool one) {
+    if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, true>);
+    if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 2, false>);
+    return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, false>);
+}
+
+template <int NR>
+static const void* pick_nr(bool vp, bool reset, int vpl, bool one) {
+    if (vp) return reset ? pick_step<NR, true, true>(vpl, one) : pick_step<NR, true, false>(vpl, one);
+    return reset ? pick_step<NR, false, true>(vpl, one) : pick_step<NR, false, false>(vpl, one);
+}
+
+const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step) {
+    switch (nr_class) {
+        case 4: return pick_nr<4>(vp, reset, vpl, one_step);
+        case 6: return pick_nr<6>(vp, reset, vpl, one_step);
+        default: return pick_nr<8>(vp, reset, vpl, one_step);
+    }
+}
+
+const void* fold_kernel() { return reinterpret_cast<const void*>(&k_fold); }
+const void* advance_kernel() { return reinterpret_cast<const void*>(&k_advance); }
+const void* set_step_kernel() { return reinterpret_cast<const void*>(&k_set_step); }
+const void* set_targets_kernel() { return reinterpret_cast<const void*>(&k_set_targets); }
+const void* reset_mask_kernel() { return reinterpret_cast<const void*>(&k_reset_mask); }
+const void* reset_scan_kernel() { return reinterpret_cast<const void*>(&k_reset_scan); }
+const void* reset_scatter_kernel() { return reinterpret_cast<const void*>(&k_reset_scatter); }
+const void* clear_slots_kernel() { return reinterpret_cast<const void*>(&k_clear_slots); }
+
+}  // namespace ag

@@ -1,0 +1,362 @@
+// ag_step.h -- per-vehicle device math of the batched multirotor step (gfx950).
+//
+// One lane owns one vehicle; everything here is straight-line FP32 scalar
+// code on registers (the 3x3 algebra is not a dense contraction, so no MFMA).
+// The three command modes share one branch-free path with selects, so a
+// wavefront holding a mix of modes never diverges.
+//
+// The controller follows Sec. IV of Kulkarni et al. (arXiv 2305.16510) with
+// these algebraic rewrites, each exact in real arithmetic:
+//   * eqs. (8)-(9) are evaluated trig-free: with h = sqrt(F_x^2 + F_z^2) and
+//     n = |F|, cos(theta_d) = F_z/h, sin(theta_d) = F_x/h, cos(phi_d) = h/n,
+//     sin(phi_d) = -F_y/n (theta_d = 0 if h = 0, phi_d = 0 if n = 0);
+//   * eq. (1) is never formed: e_R of eq. (3) needs only six entries of
+//     R_d^T R = T^T (R_z(psi)^T R) with T = R_y(theta_d) R_x(phi_d);
+//   * eqs. (1)+(2) give Omega_d = psidot_d R_d^T e3, hence eq. (4) becomes
+//     e_Omega = Omega - psidot_d R^T e3;
+//   * position and velocity errors are rotated into the reference yaw frame
+//     before the (x-y symmetric) gains are applied.
+// Allocation uses a unit-arm table per rotor layout: u = clip(A1^+ (f, M_x/l,
+// M_y/l, M_z)), applied wrench (sum u, l (A1 u)_1, l (A1 u)_2, (A1 u)_3).
+// Integration is semi-implicit Euler with quaternion renormalisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef AG_DEV
+#define AG_DEV __device__ __forceinline__
+#endif
+
+namespace ag {
+
+// ---- per-group table (floats), staged in LDS by every block ---------------
+constexpr int GSTRIDE = 96;       // floats per group entry (384 B, 16-B aligned rows)
+constexpr int G_APINV = 0;        // 8 rotors x float4: unit-arm pseudo-inverse rows
+constexpr int G_ACOL = 32;        // 8 rotors x float4: unit-arm allocation columns
+constexpr int G_UMIN = 64;
+constexpr int G_UMAX = 65;
+constexpr int G_ARM = 66;
+constexpr int G_INV_ARM = 67;
+constexpr int G_MASS = 68;
+constexpr int G_INV_MASS = 69;
+constexpr int G_J = 70;           // 3
+constexpr int G_JINV = 73;        // 3
+constexpr int G_GAINS = 76;       // 10
+constexpr int G_NR = 86;          // rotor count, as float
+
+// ---- per-vehicle parameter rows (vparams) ---------------------------------
+constexpr int VP_MASS = 0, VP_J = 1, VP_GAINS = 4, VP_ARM = 14, VP_UMAX = 15;
+
+struct Params {
+    float m, inv_m;
+    float J0, J1, J2, Ji0, Ji1, Ji2;
+    float kx_xy, kx_z, kv_xy, kv_z;
+    float kR0, kR1, kR2, kW0, kW1, kW2;
+    float arm, inv_arm, umin, umax;
+    int nr;
+};
+
+// Derived command: the 4 raw target values plus cos/sin of the command
+// angles (psi_d in position mode, phi_d in attitude mode; theta_d).
+struct Cmd {
+    int mode;
+    float t0, t1, t2, t3;
+    float ca, sa, cb, sb;
+};
+
+struct Wrench {
+    float f, M0, M1, M2;       // commanded
+    float fa, Ma0, Ma1, Ma2;   // applied after clamping
+};
+
+template <bool VP>
+AG_DEV void load_params(Params& P, const float* __restrict__ gt, const float* __restrict__ vp,
+                        int64_t ld, int64_t i) {
+    P.umin = gt[G_UMIN];
+    P.nr = (int)gt[G_NR];
+    if constexpr (VP) {
+        P.m = vp[VP_MASS * ld + i];
+        P.J0 = vp[(VP_J + 0) * ld + i];
+        P.J1 = vp[(VP_J + 1) * ld + i];
+        P.J2 = vp[(VP_J + 2) * ld + i];
+        P.kx_xy = vp[(VP_GAINS + 0) * ld + i];
+        P.kx_z = vp[(VP_GAINS + 1) * ld + i];
+        P.kv_xy = vp[(VP_GAINS + 2) * ld + i];
+        P.kv_z = vp[(VP_GAINS + 3) * ld + i];
+        P.kR0 = vp[(VP_GAINS + 4) * ld + i];
+        P.kR1 = vp[(VP_GAINS + 5) * ld + i];
+        P.kR2 = vp[(VP_GAINS + 6) * ld + i];
+        P.kW0 = vp[(VP_GAINS + 7) * ld + i];
+        P.kW1 = vp[(VP_GAINS + 8) * ld + i];
+        P.kW2 = vp[(VP_GAINS + 9) * ld + i];
+        P.arm = vp[VP_ARM * ld + i];
+        P.umax = vp[VP_UMAX * ld + i];
+        P.inv_m = 1.0f / P.m;
+        P.Ji0 = 1.0f / P.J0;
+        P.Ji1 = 1.0f / P.J1;
+        P.Ji2 = 1.0f / P.J2;
+        P.inv_arm = 1.0f / P.arm;
+    } else {
+        P.m = gt[G_MASS];
+        P.inv_m = gt[G_INV_MASS];
+        P.J0 = gt[G_J + 0];
+        P.J1 = gt[G_J + 1];
+        P.J2 = gt[G_J + 2];
+        P.Ji0 = gt[G_JINV + 0];
+        P.Ji1 = gt[G_JINV + 1];
+        P.Ji2 = gt[G_JINV + 2];
+        P.kx_xy = gt[G_GAINS + 0];
+        P.kx_z = gt[G_GAINS + 1];
+        P.kv_xy = gt[G_GAINS + 2];
+        P.kv_z = gt[G_GAINS + 3];
+        P.kR0 = gt[G_GAINS + 4];
+        P.kR1 = gt[G_GAINS + 5];
+        P.kR2 = gt[G_GAINS + 6];
+        P.kW0 = gt[G_GAINS + 7];
+        P.kW1 = gt[G_GAINS + 8];
+        P.kW2 = gt[G_GAINS + 9];
+        P.arm = gt[G_ARM];
+        P.inv_arm = gt[G_INV_ARM];
+        P.umax = gt[G_UMAX];
+    }
+}
+
+AG_DEV void derive_cmd(Cmd& C, int mode, float t0, float t1, float t2, float t3) {
+    C.mode = mode;
+    C.t0 = t0; C.t1 = t1; C.t2 = t2; C.t3 = t3;
+    // position mode: angle a = psi_d; attitude mode: a = phi_d, b = theta_d.
+    const float a = (mode == 0) ? t3 : ((mode == 2) ? t0 : 0.0f);
+    const float b = (mode == 2) ? t1 : 0.0f;
+    sincosf(a, &C.sa, &C.ca);
+    sincosf(b, &C.sb, &C.cb);
+}
+
+// One step of one vehicle.  s: x0..2, v3..5, q6..9 (w,x,y,z), W10..12.
+// gt points at the vehicle's group entry (LDS).  Returns the number of
+// rotors whose raw command fell outside [u_min, u_max]; fills W (commanded
+// and applied wrench) and u (clamped thrusts, zero-padded) when requested.
+template <int NR, bool WANT_W, bool WANT_U>
+AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
+                float dt, float g, Wrench* W, float* u_out) {
+    const float qw = s[6], qx = s[7], qy = s[8], qz = s[9];
+    // ---- R(q), unit-norm form --------------------------------------------
+    const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+    const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+    const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+    const float R00 = 1.0f - 2.0f * (yy + zz), R01 = 2.0f * (xy - wz), R02 = 2.0f * (xz + wy);
+    const float R10 = 2.0f * (xy + wz), R11 = 1.0f - 2.0f * (xx + zz), R12 = 2.0f * (yz - wx);
+    const float R20 = 2.0f * (xz - wy), R21 = 2.0f * (yz + wx), R22 = 1.0f - 2.0f * (xx + yy);
+
+    // ---- current yaw (Z-Y-X), trig-free -----------------------------------
+    const float r2 = R00 * R00 + R10 * R10;
+    const bool yok = r2 > 0.0f;
+    const float ir = rsqrtf(r2);
+    const float cpsi = yok ? R00 * ir : 1.0f;
+    const float spsi = yok ? R10 * ir : 0.0f;
+
+    const int mode = C.mode;
+    const bool m0 = mode == 0, m1 = mode == 1, m2 = mode == 2, m3 = mode == 3;
+
+    // ---- reference yaw frame: psi_d (position) or current psi -------------
+    const float cr = m0 ? C.ca : cpsi;
+    const float sr = m0 ? C.sa : spsi;
+
+    // ---- commanded force in the reference frame (position / velocity) -----
+    const float vx = s[3], vy = s[4], vz = s[5];
+    const float vVx = cr * vx + sr * vy;
+    const float vVy = cr * vy - sr * vx;
+    const float dxE = C.t0 - s[0], dyE = C.t1 - s[1], dzE = C.t2 - s[2];
+    const float ex = m0 ? (cr * dxE + sr * dyE) : 0.0f;
+    const float ey = m0 ? (cr * dyE - sr * dxE) : 0.0f;
+    const float ez = m0 ? dzE : 0.0f;
+    const float wvx = (m1 ? C.t0 : 0.0f) - vVx;
+    const float wvy = (m1 ? C.t1 : 0.0f) - vVy;
+    const float wvz = (m1 ? C.t2 : 0.0f) - vz;
+    const float ax = P.kx_xy * ex + P.kv_xy * wvx;
+    const float ay = P.kx_xy * ey + P.kv_xy * wvy;
+    const float az = P.kx_z * ez + P.kv_z * wvz;
+    const float Fx = P.m * ax, Fy = P.m * ay, Fz = P.m * (az + g);
+
+    // ---- tilt from force, eqs. (8)-(9) without trig -----------------------
+    const float h2 = Fx * Fx + Fz * Fz;
+    const float n2 = h2 + Fy * Fy;
+    const bool hok = h2 > 0.0f, nok = n2 > 0.0f;
+    const float ih = rsqrtf(h2), inn = rsqrtf(n2);
+    const float hh = hok ? h2 * ih : 0.0f;
+    float cth = hok ? Fz * ih : 1.0f;
+    float sth = hok ? Fx * ih : 0.0f;
+    float cph = nok ? hh * inn : 1.0f;
+    float sph = nok ? -Fy * inn : 0.0f;
+    cth = m2 ? C.cb : cth;
+    sth = m2 ? C.sb : sth;
+    cph = m2 ? C.ca : cph;
+    sph = m2 ? C.sa : sph;
+
+    // ---- P = R_z(psi_ref)^T R ---------------------------------------------
+    const float P00 = cr * R00 + sr * R10, P01 = cr * R01 + sr * R11, P02 = cr * R02 + sr * R12;
+    const float P10 = cr * R10 - sr * R00, P11 = cr * R11 - sr * R01, P12 = cr * R12 - sr * R02;
+    const float P20 = R20, P21 = R21, P22 = R22;
+
+    // ---- thrust: projection of F on b3 (modes 0, 1); command otherwise -----
+    const float fproj = Fx * P02 + Fy * P12 + Fz * P22;
+    float f = (m0 || m1) ? fproj : (m2 ? C.t3 : (m3 ? C.t0 : 0.0f));
+
+    // ---- e_R = 1/2 vee(E - E^T), E = T^T P, T = R_y(theta) R_x(phi) --------
+    const float T01 = sth * sph, T02 = sth * cph;
+    const float T21 = cth * sph, T22 = cth * cph;
+    const float E21 = T02 * P01 - sph * P11 + T22 * P21;
+    const float E12 = T01 * P02 + cph * P12 + T21 * P22;
+    const float E02 = cth * P02 - sth * P22;
+    const float E20 = T02 * P00 - sph * P10 + T22 * P20;
+    const float E10 = T01 * P00 + cph * P10 + T21 * P20;
+    const float E01 = cth * P01 - sth * P21;
+    const float eR0 = 0.5f * (E21 - E12);
+    const float eR1 = 0.5f * (E02 - E20);
+    const float eR2 = 0.5f * (E10 - E01);
+
+    // ---- e_Omega = Omega - psidot_d R^T e3 ---------------------------------
+    const float psidot = m1 ? C.t3 : (m2 ? C.t2 : 0.0f);
+    const float w0 = s[10], w1 = s[11], w2 = s[12];
+    const float eW0 = w0 - psidot * R20;
+    const float eW1 = w1 - psidot * R21;
+    const float eW2 = w2 - psidot * R22;
+
+    // ---- M = -kR e_R - kW e_Omega + Omega x J Omega, eq. (5) ---------------
+    const float JW0 = P.J0 * w0, JW1 = P.J1 * w1, JW2 = P.J2 * w2;
+    const float gy0 = w1 * JW2 - w2 * JW1;
+    const float gy1 = w2 * JW0 - w0 * JW2;
+    const float gy2 = w0 * JW1 - w1 * JW0;
+    float M0 = -P.kR0 * eR0 - P.kW0 * eW0 + gy0;
+    float M1 = -P.kR1 * eR1 - P.kW1 * eW1 + gy1;
+    float M2 = -P.kR2 * eR2 - P.kW2 * eW2 + gy2;
+    const bool known = m0 || m1 || m2 || m3;
+    M0 = m3 ? C.t1 : (known ? M0 : 0.0f);
+    M1 = m3 ? C.t2 : (known ? M1 : 0.0f);
+    M2 = m3 ? C.t3 : (known ? M2 : 0.0f);
+
+    // ---- allocation and clamping ------------------------------------------
+    const float a1 = M0 * P.inv_arm, a2 = M1 * P.inv_arm;
+    float fa = 0.0f, Ma0 = 0.0f, Ma1 = 0.0f, Ma2 = 0.0f;
+    int nsat = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
+        const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
+        const float raw = ap.x * f + ap.y * a1 + ap.z * a2 + ap.w * M2;
+        const bool act = r < P.nr;
+        const float u = act ? fminf(fmaxf(raw, P.umin), P.umax) : 0.0f;
+        nsat += (act && (raw < P.umin || raw > P.umax)) ? 1 : 0;
+        fa += u * ac.x;
+        Ma0 += u * ac.y;
+        Ma1 += u * ac.z;
+        Ma2 += u * ac.w;
+        if constexpr (WANT_U) u_out[r] = u;
+    }
+    Ma0 *= P.arm;
+    Ma1 *= P.arm;
+    if constexpr (WANT_W) {
+        W->f = f; W->M0 = M0; W->M1 = M1; W->M2 = M2;
+        W->fa = fa; W->Ma0 = Ma0; W->Ma1 = Ma1; W->Ma2 = Ma2;
+    }
+
+    // ---- semi-implicit Euler ----------------------------------------------
+    const float acc = fa * P.inv_m;
+    const float nvx = vx + dt * (acc * R02);
+    const float nvy = vy + dt * (acc * R12);
+    const float nvz = vz + dt * (acc * R22 - g);
+    s[0] = s[0] + dt * nvx;
+    s[1] = s[1] + dt * nvy;
+    s[2] = s[2] + dt * nvz;
+    s[3] = nvx; s[4] = nvy; s[5] = nvz;
+    const float nw0 = w0 + dt * ((Ma0 - gy0) * P.Ji0);
+    const float nw1 = w1 + dt * ((Ma1 - gy1) * P.Ji1);
+    const float nw2 = w2 + dt * ((Ma2 - gy2) * P.Ji2);
+    s[10] = nw0; s[11] = nw1; s[12] = nw2;
+    // q <- normalize(q + dt/2 q (x) (0, Omega+))
+    const float hd = 0.5f * dt;
+    const float dqw = -(qx * nw0 + qy * nw1 + qz * nw2);
+    const float dqx = qw * nw0 + (qy * nw2 - qz * nw1);
+    const float dqy = qw * nw1 + (qz * nw0 - qx * nw2);
+    const float dqz = qw * nw2 + (qx * nw1 - qy * nw0);
+    const float tw = qw + hd * dqw, tx = qx + hd * dqx, ty = qy + hd * dqy, tz = qz + hd * dqz;
+    const float iq = rsqrtf(tw * tw + tx * tx + ty * ty + tz * tz);
+    s[6] = tw * iq; s[7] = tx * iq; s[8] = ty * iq; s[9] = tz * iq;
+    return nsat;
+}
+
+// ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
+constexpr uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u;
+constexpr uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u;
+constexpr uint32_t TAG_MASK = 0x4D41534Bu, TAG_DRAW = 0x44520000u;
+
+AG_DEV uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)PHILOX_M0 * c.x;
+        const uint64_t p1 = (uint64_t)PHILOX_M1 * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    return c;
+}
+
+// Reset decision of global vehicle gi before global step t: word (t mod 4) of
+// Philox(counter = (gi, lo(t/4), hi(t/4), TAG_MASK)) compared with thr.
+AG_DEV bool reset_mask(uint32_t gi, int64_t t, uint32_t k0, uint32_t k1, uint64_t thr) {
+    const uint64_t tb = (uint64_t)t >> 2;
+    const uint4 w = philox(make_uint4(gi, (uint32_t)tb, (uint32_t)(tb >> 32), TAG_MASK), k0, k1);
+    const int sel = (int)(t & 3);
+    const uint32_t word = sel == 0 ? w.x : (sel == 1 ? w.y : (sel == 2 ? w.z : w.w));
+    return (uint64_t)word < thr;
+}
+
+AG_DEV float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }   // 2^-24
+
+// Redraw state s and goal (gx, gy, gz) for global vehicle gi at step t.
+// Words 0-2 position, 3-5 goal, 6 tilt axis angle, 7 tilt, 8 yaw, Box-Muller
+// pairs (9,10), (11,12), (13,14) -> 3 velocity and 3 body-rate normals.
+AG_DEV void redraw(float (&s)[13], float& gx, float& gy, float& gz, uint32_t gi, int64_t t,
+                   uint32_t k0, uint32_t k1, const float* lo, const float* hi) {
+    const uint64_t tu = (uint64_t)t;
+    float u[16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint4 w = philox(make_uint4(gi, (uint32_t)tu, (uint32_t)(tu >> 32), TAG_DRAW | j), k0, k1);
+        u[4 * j + 0] = u24(w.x);
+        u[4 * j + 1] = u24(w.y);
+        u[4 * j + 2] = u24(w.z);
+        u[4 * j + 3] = u24(w.w);
+    }
+    s[0] = lo[0] + (hi[0] - lo[0]) * u[0];
+    s[1] = lo[1] + (hi[1] - lo[1]) * u[1];
+    s[2] = lo[2] + (hi[2] - lo[2]) * u[2];
+    gx = lo[0] + (hi[0] - lo[0]) * u[3];
+    gy = lo[1] + (hi[1] - lo[1]) * u[4];
+    gz = lo[2] + (hi[2] - lo[2]) * u[5];
+    // angles in units of pi: beta = -1 + 2 u6, yaw = -1 + 2 u8 (both exact in FP32)
+    float cb, sb, ct, st, cy, sy;
+    sincospif(-1.0f + 2.0f * u[6], &sb, &cb);
+    sincospif(u[7] * (1.0f / 12.0f), &st, &ct);        // tau / 2 = (pi/6) u7 / 2
+    sincospif(0.5f * (-1.0f + 2.0f * u[8]), &sy, &cy); // psi / 2
+    const float b1 = st * cb, b2 = st * sb;
+    s[6] = cy * ct;
+    s[7] = cy * b1 - sy * b2;
+    s[8] = cy * b2 + sy * b1;
+    s[9] = sy * ct;
+    float nrm[6];
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const float r = sqrtf(-2.0f * logf(1.0f - u[9 + 2 * p]));
+        float sn, cs;
+        sincospif(2.0f * u[10 + 2 * p], &sn, &cs);
+        nrm[2 * p] = r * cs;
+        nrm[2 * p + 1] = r * sn;
+    }
+    s[3] = 0.5f * nrm[0]; s[4] = 0.5f * nrm[1]; s[5] = 0.5f * nrm[2];
+    s[10] = 0.2f * nrm[3]; s[11] = 0.2f * nrm[4]; s[12] = 0.2f * nrm[5];
+}
+
+}  // namespace ag

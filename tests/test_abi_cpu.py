@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and the host logic (workspace sizing and
+argument validation) behaves as documented."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ag.h")).read()
+    return sorted(set(re.findall(r"\b(ag_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2305_16510_amd import lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libag.so not built")
+    return L
+
+
+def test_header_and_binding_agree(lib):
+    assert header_functions() == sorted(lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = lib.load()
+    for name in header_functions():
+        assert hasattr(L, name), name
+    out = os.popen(f"nm -D --defined-only {lib.LIB_PATH}").read()
+    for name in header_functions():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def _cfg(lib, n=1000, groups=None, **kw):
+    import workloads
+    from paper_2305_16510_amd.sim import _group_array
+    groups = groups or [workloads.Group(0, n)]
+    arr = _group_array(groups)
+    c = lib.Config()
+    c.n, c.ld, c.dt, c.g = n, n, 0.01, 9.81
+    c.n_groups, c.groups = len(groups), arr
+    c.state = c.mode = c.target = C.c_void_p(0x1000)     # never dereferenced on the host
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c, arr
+
+
+def test_workspace_size_grows_with_n_and_scratch(lib):
+    L = lib.load()
+    sizes = []
+    for n, scratch in ((1000, 0), (100_000, 0), (100_000, 1)):
+        c, _keep = _cfg(lib, n=n, autotune_scratch=scratch)
+        b = C.c_size_t()
+        assert L.ag_workspace_size(C.byref(c), C.byref(b)) == lib.AG_OK
+        assert b.value % 256 == 0
+        sizes.append(b.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+    assert sizes[2] - sizes[1] >= 17 * 100_000 * 4
+
+
+@pytest.mark.parametrize("field,value", [("n", 0), ("ld", 10), ("dt", 0.0), ("reset_prob", 1.5),
+                                         ("index_base", 2 ** 32)])
+def test_invalid_config_rejected_before_any_device_work(lib, field, value):
+    L = lib.load()
+    c, _keep = _cfg(lib, **{field: value})
+    b = C.c_size_t()
+    assert L.ag_workspace_size(C.byref(c), C.byref(b)) == lib.AG_E_INVALID
+    h = C.c_void_p()
+    assert L.ag_create(C.byref(c), C.c_void_p(0x100000), C.c_size_t(1 << 30), C.byref(h)) == lib.AG_E_INVALID
+    assert not h.value
+
+
+def test_bad_group_layouts_rejected(lib):
+    import workloads
+    L = lib.load()
+    b = C.c_size_t()
+    for groups in ([workloads.Group(0, 500), workloads.Group(600, 400)],      # gap
+                   [workloads.Group(0, 1000, n_rotors=5)],                     # rotor count
+                   [workloads.Group(0, 1000, u_min=2.0, u_max=1.0)],           # bounds
+                   [workloads.Group(0, 999)]):                                  # coverage
+        c, _keep = _cfg(lib, groups=groups)
+        assert L.ag_workspace_size(C.byref(c), C.byref(b)) == lib.AG_E_INVALID
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    L = lib.load()
+    assert L.ag_step(None, 1) == lib.AG_E_INVALID
+    assert L.ag_sync(None) == lib.AG_E_INVALID
+    assert L.ag_destroy(None) == lib.AG_E_INVALID
+    assert L.ag_status_string(2) == b"HIP error"

@@ -1,0 +1,222 @@
+"""GPU parity of the step against the FP64 oracle, through the C ABI.
+
+Tolerances (stated for the method): per-step thrust and moment within 1e-5
+relative, with scale floors m g and m g l (measured at the GPU's own FP32
+state); position within 1e-4 m after 500 position-mode steps; integer
+outputs bit-exact; every execution policy bitwise identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from parity import need_gpu, oracle_inputs, to_vm64, wrench_errors, near_clamp, same_rotation_err
+
+pytestmark = pytest.mark.gpu
+
+F64 = torch.float64
+
+
+def make_sim(wl, **kw):
+    from paper_2305_16510_amd.sim import Sim
+    return Sim.from_workload(wl, **kw)
+
+
+def run_per_step_with_wrench(wl, steps, every=1):
+    """Run `steps` plain per-step launches; return GPU pre-step states and
+    wrench outputs (host FP64) every `every` steps, and the final state."""
+    sim = make_sim(wl, outputs=True)
+    sim.set_exec(kind=0, block=256, use_graph=0)
+    pres, ws = [], []
+    for t in range(steps):
+        keep = t % every == 0
+        if keep:
+            pres.append(sim.state.clone())
+        sim.step(1)
+        if keep:
+            ws.append(sim.wrench.clone())
+    sim.sync()
+    final = sim.state.clone()
+    sim.close()
+    return [to_vm64(p) for p in pres], [to_vm64(w) for w in ws], to_vm64(final)
+
+
+def test_c1_per_step_wrench_parity():
+    """C1 (1,024 quads, position mode): commanded and applied wrench of every
+    one of 500 steps, each evaluated by the oracle at the GPU's FP32 state."""
+    need_gpu()
+    wl = workloads.c1_parity()
+    pres, ws, _ = run_per_step_with_wrench(wl, 500, every=5)
+    _, mode, tgt, fleet = oracle_inputs(wl)
+    worst = torch.zeros(4, dtype=F64)
+    kinks = 0
+    for pre, W in zip(pres, ws):
+        _, info = oracle.step.step(pre, mode, tgt, fleet, wl.dt, wl.g)
+        nk = near_clamp(info, fleet)
+        kinks += int(nk.sum())
+        errs = wrench_errors(W, info, fleet, wl.g, near_kink=nk)
+        worst = torch.maximum(worst, torch.stack([e.max() for e in errs]))
+    print("max rel err f, M, f', M':", worst.tolist(), "near-clamp vehicle-steps:", kinks)
+    assert worst.max() <= 1e-5
+
+
+@pytest.mark.parametrize("policy", ["per_step", "fused_graph"])
+def test_c1_position_after_500_steps(policy):
+    """C1: FP32 GPU positions after 500 steps within 1e-4 m of the FP64 oracle."""
+    need_gpu()
+    wl = workloads.c1_parity()
+    sim = make_sim(wl)
+    if policy == "per_step":
+        sim.set_exec(kind=0, block=256, use_graph=0)
+    else:
+        sim.set_exec(kind=1, block=128, vpl=1, k=25, grid=0, use_graph=1)
+    sim.step(500)
+    sim.sync()
+    gpu = to_vm64(sim.state)
+    sim.close()
+    s0, mode, tgt, fleet = oracle_inputs(wl)
+    ref, _, _ = oracle.step.rollout(s0, mode, tgt, fleet, wl.dt, wl.g, 500)
+    dx = (gpu[:, 0:3] - ref[:, 0:3]).norm(dim=-1)
+    print("position error after 500 steps: max %.3e  p99 %.3e  median %.3e" %
+          (dx.max(), dx.quantile(0.99), dx.median()))
+    assert dx.max() <= 1e-4
+    assert same_rotation_err(gpu[:, 6:10], ref[:, 6:10]).max() <= 1e-4
+
+
+def mixed_workload(n=3001, seed=21):
+    """All command modes, including the wrench test mode and an unknown code,
+    with a ragged tail (n not a multiple of any block size)."""
+    wl = workloads.c2_scale(n=n, seed=seed, steps=200)
+    rng = np.random.default_rng(seed)
+    sel = rng.random(n)
+    w3 = sel < 0.08
+    wl.mode[w3] = 3
+    wl.target[:, w3] = np.stack([rng.uniform(0, 20, w3.sum()), rng.normal(0, 0.05, w3.sum()),
+                                 rng.normal(0, 0.05, w3.sum()), rng.normal(0, 0.01, w3.sum())]
+                                ).astype(np.float32)
+    bad = (sel > 0.99)
+    wl.mode[bad] = 9
+    pos = wl.mode == 0
+    wl.target[:, pos] = np.concatenate([rng.uniform(-3, 3, (3, pos.sum())),
+                                        rng.uniform(-3, 3, (1, pos.sum()))]).astype(np.float32)
+    return wl
+
+
+def test_all_modes_per_step_wrench_parity():
+    need_gpu()
+    wl = mixed_workload()
+    pres, ws, _ = run_per_step_with_wrench(wl, 120, every=4)
+    _, mode, tgt, fleet = oracle_inputs(wl)
+    worst = torch.zeros(4, dtype=F64)
+    for pre, W in zip(pres, ws):
+        finite = torch.isfinite(pre).all(-1)
+        _, info = oracle.step.step(pre, mode, tgt, fleet, wl.dt, wl.g)
+        nk = near_clamp(info, fleet)
+        errs = wrench_errors(W, info, fleet, wl.g, near_kink=nk)
+        worst = torch.maximum(worst, torch.stack([e[finite].max() for e in errs]))
+    print("all modes: max rel err f, M, f', M':", worst.tolist())
+    assert worst.max() <= 1e-5
+    unknown = torch.as_tensor(wl.mode == 9)
+    assert torch.equal(ws[-1][unknown, 0:4], torch.zeros(int(unknown.sum()), 4, dtype=F64))
+
+
+def test_all_modes_one_step_state_parity():
+    """One step from the same FP32 state: every state component within FP32
+    rounding of the oracle's step (relative 1e-5 with unit floor)."""
+    need_gpu()
+    wl = mixed_workload(n=4099, seed=22)
+    sim = make_sim(wl)
+    sim.set_exec(kind=0, block=64, use_graph=0)
+    sim.step(1)
+    sim.sync()
+    gpu = to_vm64(sim.state)
+    sim.close()
+    s0, mode, tgt, fleet = oracle_inputs(wl)
+    ref, _ = oracle.step.step(s0, mode, tgt, fleet, wl.dt, wl.g)
+    err = ((gpu - ref).abs() / torch.clamp(ref.abs(), min=1.0)).max()
+    print("one-step max rel err:", float(err))
+    assert err <= 1e-5
+
+
+def test_free_fall_closed_form_on_gpu():
+    """Wrench mode with zero command: the GPU integrator reproduces the
+    discrete free-fall closed form (FP32 rounding only)."""
+    need_gpu()
+    n, T, dt = 777, 200, 0.01
+    wl = workloads.c1_parity(n=n, seed=30)
+    wl.mode[:] = 3
+    wl.target[:] = 0.0
+    sim = make_sim(wl)
+    sim.set_exec(kind=1, block=64, vpl=2, k=7, use_graph=1)
+    sim.step(T)
+    sim.sync()
+    gpu = to_vm64(sim.state)
+    sim.close()
+    s0 = torch.as_tensor(wl.state0.T.astype(np.float64))
+    e3 = torch.tensor([0, 0, 1.0], dtype=F64)
+    g = float(np.float32(9.81))
+    v_exact = s0[:, 3:6] - T * g * dt * e3
+    x_exact = s0[:, 0:3] + T * dt * s0[:, 3:6] - g * dt * dt * T * (T + 1) / 2 * e3
+    assert (gpu[:, 3:6] - v_exact).abs().max() < 2e-5
+    assert (gpu[:, 0:3] - x_exact).abs().max() < 2e-5
+
+
+POLICIES = [
+    dict(kind=0, block=64, use_graph=0),
+    dict(kind=1, block=64, vpl=1, k=1, grid=0, use_graph=0),
+    dict(kind=1, block=128, vpl=2, k=7, grid=0, use_graph=1),
+    dict(kind=1, block=256, vpl=1, k=16, grid=8, use_graph=1),
+    dict(kind=1, block=512, vpl=2, k=50, grid=24, use_graph=1),
+    dict(kind=1, block=192, vpl=1, k=33, grid=0, use_graph=0),
+]
+
+
+def test_every_policy_bitwise_identical():
+    """Per-step launches, fused launches of any k, block, vehicles per lane,
+    persistent grid, with or without graphs: identical bits."""
+    need_gpu()
+    wl = mixed_workload(n=20_011, seed=23)
+    finals = []
+    for pol in POLICIES:
+        sim = make_sim(wl)
+        sim.set_exec(**pol)
+        sim.step(60)
+        sim.step(40)
+        sim.sync()
+        finals.append(sim.state.clone())
+        assert sim.step_counter == 100
+        sim.close()
+    for pol, f in zip(POLICIES[1:], finals[1:]):
+        assert torch.equal(f, finals[0]), pol
+
+
+def test_repeat_runs_identical():
+    need_gpu()
+    wl = mixed_workload(n=5000, seed=24)
+    outs = []
+    for _ in range(2):
+        sim = make_sim(wl)
+        sim.set_exec(kind=1, block=256, vpl=1, k=10, use_graph=1)
+        sim.step(100)
+        sim.sync()
+        outs.append(sim.state.clone())
+        sim.close()
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_tiny_batches_and_ragged_tails():
+    """n = 1, 63, 65: tails shorter than a wavefront; parity of 30 steps."""
+    need_gpu()
+    for n in (1, 63, 65):
+        wl = mixed_workload(n=n, seed=25 + n)
+        sim = make_sim(wl)
+        sim.set_exec(kind=1, block=64, vpl=2, k=4, use_graph=1)
+        sim.step(30)
+        sim.sync()
+        gpu = to_vm64(sim.state)
+        sim.close()
+        s0, mode, tgt, fleet = oracle_inputs(wl)
+        ref, _, _ = oracle.step.rollout(s0, mode, tgt, fleet, wl.dt, wl.g, 30)
+        err = ((gpu[:, :6] - ref[:, :6]).abs() / torch.clamp(ref[:, :6].abs(), min=1.0)).max()
+        assert err < 1e-4, (n, float(err))
