@@ -81,7 +81,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--exec", type=str, default="", help="fixed fused policy 'block,vpl,k,grid' (skips tuning)")
     ap.add_argument("--cpu-sample", type=int, default=65_536)
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -205,6 +207,16 @@ def main():
 
     sim.close()
     del sim
+    if args.copy_calib_mib:
+        # a plain device copy of known size: calibrates the HBM byte counters
+        nb = args.copy_calib_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        sync()
+        out["copy_calibration"] = {"bytes_read": nb, "bytes_written": nb, "dispatches": 3}
+        del src, dst
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, args.cpu_steps)

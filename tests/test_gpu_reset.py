@@ -1,0 +1,116 @@
+"""Counter-based resets on the GPU: mask, indices and counts bit-exact
+against the oracle's Philox4x32-10; redrawn states within FP32 rounding;
+automatic resets inside fused launches identical to explicit resets."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from parity import need_gpu, to_vm64
+
+pytestmark = pytest.mark.gpu
+F64 = torch.float64
+LO, HI = (-5.0, -5.0, -5.0), (5.0, 5.0, 5.0)
+
+
+def make_sim(wl, **kw):
+    from paper_2305_16510_amd.sim import Sim
+    return Sim.from_workload(wl, **kw)
+
+
+def mixed(n, seed):
+    wl = workloads.c2_scale(n=n, seed=seed)
+    wl.reset_prob = 0.01
+    wl.seed = 0xDEADBEEF12345 + seed
+    return wl
+
+
+@pytest.mark.parametrize("p,t", [(0.01, 0), (0.01, 123457), (0.3, 7)])
+def test_counter_based_reset_matches_oracle(p, t):
+    need_gpu()
+    wl = mixed(100_003, 40)
+    wl.reset_prob = p
+    base = 1000
+    sim = make_sim(wl, index_base=base)
+    mask, idx = sim.reset(step=t)
+    state = to_vm64(sim.state)
+    target = to_vm64(sim.target)
+    sim.close()
+    gidx = np.arange(wl.n) + base
+    om = oracle.reset.mask(gidx, t, wl.seed, p)
+    assert np.array_equal(mask.cpu().numpy().astype(bool), om)
+    assert np.array_equal(idx.cpu().numpy(), np.flatnonzero(om).astype(np.int32))
+    s0 = torch.as_tensor(wl.state0.T.astype(np.float64))
+    t0 = torch.as_tensor(wl.target.T.astype(np.float64))
+    keep = torch.as_tensor(~om)
+    assert torch.equal(state[keep], s0[keep]) and torch.equal(target[keep], t0[keep])
+    r = np.flatnonzero(om)
+    s_new, goal = oracle.reset.redraw(gidx[r], t, wl.seed, LO, HI)
+    err = (state[r] - s_new).abs().max()
+    print("redraw max abs err", float(err), "resets", len(r))
+    assert err <= 2e-6
+    pos = torch.as_tensor(wl.mode[r] == 0)
+    assert (target[r][pos, :3] - goal[pos]).abs().max() <= 1e-6
+    assert (target[r][pos, 3] == 0).all()
+    assert torch.equal(target[r][~pos], t0[r][~pos])
+
+
+def test_explicit_mask_reset():
+    need_gpu()
+    wl = mixed(5000, 41)
+    rng = np.random.default_rng(1)
+    m = (rng.random(wl.n) < 0.2).astype(np.uint8)
+    sim = make_sim(wl)
+    mask, idx = sim.reset(step=99, mask=torch.as_tensor(m))
+    state = to_vm64(sim.state)
+    sim.close()
+    assert np.array_equal(mask.cpu().numpy(), m)
+    assert np.array_equal(idx.cpu().numpy(), np.flatnonzero(m).astype(np.int32))
+    r = np.flatnonzero(m)
+    s_new, _ = oracle.reset.redraw(r, 99, wl.seed, LO, HI)
+    assert (state[r] - s_new).abs().max() <= 2e-6
+
+
+@pytest.mark.parametrize("policy", [dict(kind=0, block=128, use_graph=0),
+                                    dict(kind=1, block=64, vpl=2, k=9, use_graph=1),
+                                    dict(kind=1, block=256, vpl=1, k=50, grid=16, use_graph=1)])
+def test_automatic_resets_equal_explicit_resets(policy):
+    """ag_step with automatic resets == (ag_reset(t); ag_step(1)) for each t."""
+    need_gpu()
+    wl = mixed(30_001, 42)
+    wl.reset_prob = 0.05
+    a = make_sim(wl, auto_reset=True, collect_stats=True)
+    a.set_exec(**policy)
+    a.step(37)
+    a.step(13)
+    a.sync()
+    b = make_sim(wl)
+    b.set_exec(kind=0, block=256, use_graph=0)
+    n_resets = 0
+    for t in range(50):
+        _, idx = b.reset(step=t)
+        n_resets += len(idx)
+        b.step(1)
+    b.sync()
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.target, b.target)
+    st = a.stats()
+    assert st["n_resets"] == n_resets and st["steps"] == 50
+    a.close()
+    b.close()
+
+
+def test_full_size_mask_bit_exact():
+    """4,194,304 vehicles (the large randomized rollout): the reset mask and
+    indices of one step are bit-exact at full size."""
+    need_gpu()
+    n = 4_194_304
+    wl = workloads.c5_large(n=n)
+    sim = make_sim(wl)
+    mask, idx = sim.reset(step=1999)
+    om = oracle.reset.mask(np.arange(n), 1999, wl.seed, wl.reset_prob)
+    got = idx.cpu().numpy()
+    sim.close()
+    assert np.array_equal(got, np.flatnonzero(om).astype(np.int32))
+    assert abs(len(got) - 0.01 * n) < 5 * np.sqrt(0.01 * n)

@@ -1,0 +1,98 @@
+"""Batch statistics, per-vehicle flags and command validation on the GPU."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from parity import need_gpu, oracle_inputs, to_vm64
+
+pytestmark = pytest.mark.gpu
+
+
+def make_sim(wl, **kw):
+    from paper_2305_16510_amd.sim import Sim
+    return Sim.from_workload(wl, **kw)
+
+
+def test_final_state_statistics_match_host_sums():
+    need_gpu()
+    wl = workloads.c2_scale(n=50_000, seed=50)
+    sim = make_sim(wl, collect_stats=True)
+    sim.set_exec(kind=1, block=256, vpl=1, k=10, grid=64, use_graph=1)
+    sim.step(40)
+    st = sim.stats()
+    s = to_vm64(sim.state)
+    sim.close()
+    ref = oracle.stats.final_state_stats(s, wl.mode, torch.as_tensor(wl.target.T.astype(np.float64)))
+    assert st["steps"] == 40
+    assert st["n_nonfinite"] == ref["n_nonfinite"] == 0
+    assert st["n_finite"] == ref["n_finite"] and st["n_position"] == ref["n_position"]
+    assert abs(st["pos_err_sum"] - ref["pos_err_sum"]) <= 1e-6 * ref["pos_err_sum"]
+    assert abs(st["omega_sum"] - ref["omega_sum"]) <= 1e-6 * ref["omega_sum"]
+
+
+def test_saturation_count_matches_oracle_and_policy():
+    need_gpu()
+    wl = workloads.c1_parity(n=2048, seed=51)
+    counts = []
+    for pol in (dict(kind=0, block=64, use_graph=0), dict(kind=1, block=128, vpl=2, k=7, use_graph=1)):
+        sim = make_sim(wl, collect_stats=True)
+        sim.set_exec(**pol)
+        sim.step(60)
+        counts.append(sim.stats()["n_saturated"])
+        sim.close()
+    assert counts[0] == counts[1]
+    s0, mode, tgt, fleet = oracle_inputs(wl)
+    s, n_sat, n_near = s0, 0, 0
+    tabs = oracle.allocation.tables(fleet)
+    for _ in range(60):
+        s, info = oracle.step.step(s, mode, tgt, fleet, wl.dt, wl.g, tabs)
+        raw = info["u_raw"][:, :4]
+        n_sat += int(((raw < fleet.u_min[:, None]) | (raw > fleet.u_max[:, None])).sum())
+        tol = 1e-4 * fleet.u_max[:, None]
+        n_near += int((((raw - fleet.u_min[:, None]).abs() < tol) |
+                       ((raw - fleet.u_max[:, None]).abs() < tol)).sum())
+    print("saturated rotor-steps gpu", counts[0], "oracle", n_sat, "near bound", n_near)
+    assert abs(counts[0] - n_sat) <= n_near
+
+
+def test_nonfinite_vehicles_are_flagged_not_fatal():
+    need_gpu()
+    wl = workloads.c1_parity(n=1000, seed=52)
+    bad = np.array([3, 64, 500, 999])
+    wl.state0[7, bad] = np.nan
+    wl.state0[0, 10] = np.inf
+    sim = make_sim(wl, collect_stats=True, outputs=True)
+    sim.step(5)
+    st = sim.stats()
+    flags = sim.flags.cpu().numpy()
+    ok = sim.state.cpu().numpy()
+    sim.close()
+    nonfinite = np.zeros(1000, bool)
+    nonfinite[bad] = True
+    nonfinite[10] = True
+    assert st["n_nonfinite"] == 5 and st["n_finite"] == 995
+    assert np.array_equal((flags & 1).astype(bool), nonfinite)
+    assert np.isfinite(ok[:, ~nonfinite]).all()
+
+
+def test_set_targets_copies_and_counts_invalid_modes():
+    need_gpu()
+    wl = workloads.c1_parity(n=3000, seed=53)
+    sim = make_sim(wl, collect_stats=True, outputs=True)
+    new_mode = np.full(1000, 1, np.int8)
+    new_mode[::100] = 17
+    new_t = np.zeros((4, 1000), np.float32)
+    new_t[0] = 1.0
+    sim.set_targets(1000, 1000, torch.as_tensor(new_mode), torch.as_tensor(new_t))
+    sim.step(1)
+    st = sim.stats()
+    m = sim.mode.cpu().numpy()
+    t = sim.target.cpu().numpy()
+    w = sim.wrench.cpu().numpy()
+    sim.close()
+    assert st["n_invalid_mode"] == 10
+    assert np.array_equal(m[1000:2000], new_mode) and np.array_equal(m[:1000], wl.mode[:1000])
+    assert np.array_equal(t[:, 1000:2000], new_t)
+    assert np.all(w[:4, 1000:2000:100] == 0)
