@@ -69,6 +69,97 @@ def cpu_baseline(wl, n_sample, steps):
             "seconds": dt}
 
 
+def bench_adjoint(sync, reps=3):
+    """Differentiation workload: 65,536 quads, 200-step position rollout,
+    checkpoint every 20 steps; forward + hand-written adjoint."""
+    import torch
+    import workloads
+    from paper_2305_16510_amd.sim import Sim
+    wl = workloads.c4_grad()
+    T, m = wl.steps, wl.meta["ckpt_every"]
+    sim = Sim.from_workload(wl)
+    sim.rollout_forward(T, m)
+    sim.rollout_adjoint(T, m)
+    sync()
+    tf, ta = [], []
+    for _ in range(reps):
+        tf.append(event_time(sim.stream, lambda: sim.rollout_forward(T, m)))
+        ta.append(event_time(sim.stream, lambda: sim.rollout_adjoint(T, m)))
+    sim.close()
+    f, a = min(tf), min(ta)
+    log(f"adjoint: forward {f * 1e3:.2f} ms, adjoint {a * 1e3:.2f} ms for {T} steps of {wl.n} vehicles")
+    return {"workload": "65,536 quads, 200-step position rollout, checkpoint every 20, 10 gain + 13 state "
+                        "gradients per vehicle", "n_vehicles": wl.n, "steps": T,
+            "forward_s_per_step": f / T, "adjoint_s_per_step": a / T, "fwd_plus_adj_s_per_step": (f + a) / T,
+            "vehicle_steps_per_s_fwd_adj": wl.n * T / (f + a)}
+
+
+def bench_uneven(sync):
+    """48 groups (log-uniform sizes 512..131,072; 4/6/8 rotors; per-vehicle
+    parameters), 2,000 steps in one autotuned graph-replayed rollout."""
+    import workloads
+    from paper_2305_16510_amd.sim import Sim
+    wl = workloads.c3_uneven()
+    sim = Sim.from_workload(wl, autotune_scratch=True)
+    tuned = sim.autotune(32)
+    sim.prepare(wl.steps)
+    sim.raw_step(wl.steps)
+    sync()
+    t = timed(lambda: sim.raw_step(wl.steps), sync)
+    sim.close()
+    log(f"uneven groups: {wl.n} vehicles, {wl.n * wl.steps / t:.3e} vehicle-steps/s ({tuned})")
+    return {"workload": "48 uneven groups, quad/hexa/octo, per-vehicle mass/inertia/gains, position mode",
+            "n_vehicles": wl.n, "steps": wl.steps, "value": wl.n * wl.steps / t, "exec": tuned}
+
+
+def bench_large(sync):
+    """4,194,304 quads, 2,000 steps at dt = 0.005 with 1% counter-based resets
+    per step, then a forward + adjoint gain-tuning pass (100 steps) with one
+    SGD step on the first 262,144 vehicles."""
+    import torch
+    import workloads
+    from paper_2305_16510_amd.autograd import rollout_loss
+    from paper_2305_16510_amd.sim import Sim
+    wl = workloads.c5_large()
+    torch.cuda.reset_peak_memory_stats()
+    sim = Sim.from_workload(wl, auto_reset=True, collect_stats=True, autotune_scratch=True)
+    tuned = sim.autotune(16)
+    sim.prepare(wl.steps)
+    sync()
+    t = timed(lambda: sim.raw_step(wl.steps), sync)
+    st = sim.stats()
+    free, total = torch.cuda.mem_get_info()
+    peak = torch.cuda.max_memory_allocated()
+    sim.close()
+    sub = workloads.subset(wl, wl.meta["tune_subset"])
+    sub.vparams = workloads.per_vehicle_defaults(sub.n)
+    ss = Sim.from_workload(sub)
+    gains = ss.vparams[4:14].clone().requires_grad_(True)
+    x0 = ss.state.clone()
+    T = wl.meta["tune_steps"]
+
+    def tune():
+        loss = rollout_loss(ss, gains, x0, T, 20, 0.01)
+        loss.backward()
+        with torch.no_grad():
+            gains.sub_(0.05 * gains.grad).clamp_(min=1e-3)
+            gains.grad = None
+        return loss
+
+    tune()
+    sync()
+    tt = timed(tune, sync)
+    ss.close()
+    log(f"large: {wl.n * wl.steps / t:.3e} vehicle-steps/s with resets ({st['n_resets']} resets); "
+        f"tuning pass {tt * 1e3:.1f} ms; peak torch memory {peak / 2**20:.0f} MiB")
+    return {"workload": "4,194,304 quads, 2,000 steps dt=0.005, 1% counter-based resets per step",
+            "n_vehicles": wl.n, "steps": wl.steps, "value": wl.n * wl.steps / t, "exec": tuned,
+            "resets": st["n_resets"], "expected_resets": 0.01 * wl.n * wl.steps,
+            "peak_torch_allocated_bytes": peak, "device_used_bytes": total - free,
+            "tuning_pass": {"n_vehicles": sub.n, "steps": T, "seconds": tt,
+                            "what": "forward + adjoint + one SGD step on the 10 gains"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +295,9 @@ def main():
                               "workload": "2^17 quads, constant attitude or velocity commands, dt=0.01"}
         sp.close()
         log(f"paper shape 2^17: {wp.n * K / tp:.3e} vehicle-steps/s")
+        out["adjoint"] = bench_adjoint(sync)
+        out["uneven_groups"] = bench_uneven(sync)
+        out["large_resets"] = bench_large(sync)
 
     sim.close()
     del sim

@@ -770,20 +770,80 @@ ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_e
     return AG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kRolloutBlock = 64;
+
+ag_status rollout_args(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega, void* ws,
+                       size_t ws_bytes, RolloutArgs& a, LaunchShape& s) {
+    if (n_steps < 1 || ckpt_every < 1) return set_err(h, AG_E_INVALID, "n_steps and ckpt_every must be >= 1");
+    if (!h->cfg.vparams) return set_err(h, AG_E_UNSUPPORTED, "rollouts differentiate per-vehicle gains: vparams required");
+    if (!std::isfinite(w_omega)) return set_err(h, AG_E_INVALID, "w_omega must be finite");
+    size_t need = 0;
+    ag_status st = ag_rollout_workspace_size(h, n_steps, ckpt_every, &need);
+    if (st != AG_OK) return st;
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+        return set_err(h, AG_E_NOMEM, "rollout workspace missing, misaligned or too small");
+    const long long n = h->cfg.n;
+    const long long n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
+    char* base = static_cast<char*>(ws);
+    a = RolloutArgs{};
+    a.x0 = x0 ? x0 : h->cfg.state;
+    a.mode = h->cfg.mode;
+    a.target = h->cfg.target;
+    a.vparams = h->cfg.vparams;
+    a.gtab = h->gtab;
+    a.goff = h->goff;
+    a.ckpt = reinterpret_cast<float*>(base);
+    a.tape = reinterpret_cast<float*>(base + align_up((size_t)n_ckpt * AG_STATE_DIM * n * sizeof(float)));
+    a.n = n;
+    a.ld = h->cfg.ld;
+    a.n_groups = h->cfg.n_groups;
+    a.T = n_steps;
+    a.m = ckpt_every;
+    a.n_ckpt = (int)n_ckpt;
+    a.dt = h->cfg.dt;
+    a.g = h->cfg.g;
+    a.w_omega = w_omega;
+    const int span = tile_span(h, kRolloutBlock);
+    a.span = span;
+    s.span = span;
+    s.shmem = lds_bytes(span);
+    s.block = dim3(kRolloutBlock);
+    s.grid = dim3((unsigned)((n + kRolloutBlock - 1) / kRolloutBlock));
+    return AG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 ag_status ag_rollout_forward(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega,
                              void* ws, size_t ws_bytes, float* loss_out, float* final_state) {
     AG_CHECK_HANDLE(h);
-    (void)x0; (void)n_steps; (void)ckpt_every; (void)w_omega; (void)ws; (void)ws_bytes; (void)loss_out;
-    (void)final_state;
-    return set_err(h, AG_E_UNSUPPORTED, "rollout not built yet");
+    RolloutArgs a;
+    LaunchShape s;
+    ag_status st = rollout_args(h, x0, n_steps, ckpt_every, w_omega, ws, ws_bytes, a, s);
+    if (st != AG_OK) return st;
+    a.loss_out = loss_out;
+    a.final_state = final_state;
+    return launch(h, rollout_fwd_kernel(h->nr_class), s.grid, s.block, s.shmem, &a);
 }
 
 ag_status ag_rollout_adjoint(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega,
                              float seed_grad, void* ws, size_t ws_bytes, float* dgains, float* dx0) {
     AG_CHECK_HANDLE(h);
-    (void)x0; (void)n_steps; (void)ckpt_every; (void)w_omega; (void)seed_grad; (void)ws; (void)ws_bytes;
-    (void)dgains; (void)dx0;
-    return set_err(h, AG_E_UNSUPPORTED, "rollout not built yet");
+    if (!dgains || !dx0) return set_err(h, AG_E_INVALID, "dgains and dx0 are required");
+    RolloutArgs a;
+    LaunchShape s;
+    ag_status st = rollout_args(h, x0, n_steps, ckpt_every, w_omega, ws, ws_bytes, a, s);
+    if (st != AG_OK) return st;
+    a.dgains = dgains;
+    a.dx0 = dx0;
+    a.seed_grad = seed_grad / (float)h->cfg.n;
+    return launch(h, rollout_adj_kernel(h->nr_class), s.grid, s.block, s.shmem, &a);
 }
 
 ag_status ag_sync(ag_handle h) {

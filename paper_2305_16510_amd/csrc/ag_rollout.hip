@@ -1,0 +1,154 @@
+// ag_rollout.hip -- differentiable rollout of the tracking loss (gfx950).
+//
+// Forward: each lane runs its vehicle for T steps from x0 with the step
+// function of the simulator, accumulates its loss
+//   l_i = sum_{t=1..T} |x_t - goal|^2 + w_omega |Omega_t|^2
+// and writes the state every m steps to a checkpoint array.
+// Adjoint: for each checkpoint segment, last to first, the lane recomputes
+// the segment's states into a per-vehicle tape (structure-of-arrays in the
+// caller's workspace), then walks the tape backwards running the hand-
+// written reverse of each step (step_core<..., GRAD = true>), which adds the
+// loss gradient of the post-step state and pulls the adjoint back to the
+// pre-step state while accumulating the gain adjoints.  Vehicles are
+// independent, so the whole rollout of a vehicle stays in one lane: no
+// synchronisation beyond the LDS staging of the group tables.
+#include <hip/hip_runtime.h>
+
+#include "ag.h"
+#include "ag_internal.h"
+#include "ag_step.h"
+
+namespace ag {
+
+__device__ __forceinline__ int rollout_find_group(const int32_t* __restrict__ goff, int n_groups, long long i) {
+    int lo = 0, hi = n_groups;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)goff[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Stage the groups overlapping this block's vehicles; returns the vehicle's group entry.
+__device__ __forceinline__ const float* rollout_stage(const RolloutArgs& a, float* lds, int* loff, int* sh,
+                                                      long long i) {
+    const long long base = (long long)blockIdx.x * blockDim.x;
+    const long long end = base + blockDim.x < a.n ? base + blockDim.x : a.n;
+    if (threadIdx.x == 0) {
+        const int glo = a.n_groups == 1 ? 0 : rollout_find_group(a.goff, a.n_groups, base);
+        const int ghi = a.n_groups == 1 ? 0 : rollout_find_group(a.goff, a.n_groups, end - 1);
+        sh[0] = glo;
+        sh[1] = ghi - glo + 1;
+    }
+    __syncthreads();
+    const int glo = sh[0], cnt = sh[1];
+    for (int e = threadIdx.x; e < cnt * GSTRIDE; e += blockDim.x) lds[e] = a.gtab[(long long)glo * GSTRIDE + e];
+    for (int e = threadIdx.x; e <= cnt; e += blockDim.x) loff[e] = a.goff[glo + e];
+    __syncthreads();
+    int j = 0;
+    while (j + 1 < cnt && i >= (long long)loff[j + 1]) ++j;
+    return lds + j * GSTRIDE;
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
+    __shared__ int sh[2];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const float* gt = rollout_stage(a, lds, loff, sh, i);
+    if (i >= a.n) return;
+    const long long ld = a.ld, n = a.n;
+    float s[13];
+#pragma unroll
+    for (int r = 0; r < 13; ++r) s[r] = a.x0[r * ld + i];
+    Params P;
+    load_params<true>(P, gt, a.vparams, ld, i);
+    Cmd C;
+    derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
+    const float gx = C.t0, gy = C.t1, gz = C.t2;
+    double loss = 0.0;
+    for (int t = 0; t < a.T; ++t) {
+        if (t % a.m == 0) {
+            float* ck = a.ckpt + (long long)(t / a.m) * 13 * n;
+#pragma unroll
+            for (int r = 0; r < 13; ++r) ck[r * n + i] = s[r];
+        }
+        step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+        const float ex = s[0] - gx, ey = s[1] - gy, ez = s[2] - gz;
+        const float lt = ex * ex + ey * ey + ez * ez + a.w_omega * (s[10] * s[10] + s[11] * s[11] + s[12] * s[12]);
+        loss += (double)lt;
+    }
+    if (a.loss_out) a.loss_out[i] = (float)loss;
+    if (a.final_state) {
+#pragma unroll
+        for (int r = 0; r < 13; ++r) a.final_state[r * ld + i] = s[r];
+    }
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_rollout_adj(RolloutArgs a) {
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
+    __shared__ int sh[2];
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const float* gt = rollout_stage(a, lds, loff, sh, i);
+    if (i >= a.n) return;
+    const long long ld = a.ld, n = a.n;
+    Params P;
+    load_params<true>(P, gt, a.vparams, ld, i);
+    Cmd C;
+    derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
+    Adj A;
+#pragma unroll
+    for (int r = 0; r < 13; ++r) A.lam[r] = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) A.gb[r] = 0.0f;
+    A.gx = C.t0; A.gy = C.t1; A.gz = C.t2;
+    A.w_omega = a.w_omega;
+    float s[13];
+    for (int seg = a.n_ckpt - 1; seg >= 0; --seg) {
+        const int t0 = seg * a.m;
+        const int t1 = t0 + a.m < a.T ? t0 + a.m : a.T;
+        const float* ck = a.ckpt + (long long)seg * 13 * n;
+#pragma unroll
+        for (int r = 0; r < 13; ++r) s[r] = ck[r * n + i];
+        for (int t = t0; t < t1; ++t) {
+            float* tp = a.tape + (long long)(t - t0) * 13 * n;
+#pragma unroll
+            for (int r = 0; r < 13; ++r) tp[r * n + i] = s[r];
+            if (t + 1 < t1) step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+        }
+        for (int t = t1 - 1; t >= t0; --t) {
+            const float* tp = a.tape + (long long)(t - t0) * 13 * n;
+#pragma unroll
+            for (int r = 0; r < 13; ++r) s[r] = tp[r * n + i];
+            step_core<NR, false, false, true>(s, C, P, gt, a.dt, a.g, nullptr, nullptr, &A);
+        }
+    }
+    const float sc = a.seed_grad;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) a.dgains[r * ld + i] = A.gb[r] * sc;
+#pragma unroll
+    for (int r = 0; r < 13; ++r) a.dx0[r * ld + i] = A.lam[r] * sc;
+}
+
+const void* rollout_fwd_kernel(int nr_class) {
+    switch (nr_class) {
+        case 4: return reinterpret_cast<const void*>(&k_rollout_fwd<4>);
+        case 6: return reinterpret_cast<const void*>(&k_rollout_fwd<6>);
+        default: return reinterpret_cast<const void*>(&k_rollout_fwd<8>);
+    }
+}
+
+const void* rollout_adj_kernel(int nr_class) {
+    switch (nr_class) {
+        case 4: return reinterpret_cast<const void*>(&k_rollout_adj<4>);
+        case 6: return reinterpret_cast<const void*>(&k_rollout_adj<6>);
+        default: return reinterpret_cast<const void*>(&k_rollout_adj<8>);
+    }
+}
+
+}  // namespace ag

@@ -132,13 +132,27 @@ AG_DEV void derive_cmd(Cmd& C, int mode, float t0, float t1, float t2, float t3)
     sincosf(b, &C.sb, &C.cb);
 }
 
+// Reverse-mode state of one vehicle for the tracking loss
+// sum_t |x_t - goal|^2 + w_omega |Omega_t|^2 over post-step states.
+struct Adj {
+    float lam[13];     // in: adjoint of the post-step state; out: of the pre-step state
+    float gb[10];      // accumulated adjoint of the ten gains
+    float gx, gy, gz;  // goal
+    float w_omega;
+};
+
 // One step of one vehicle.  s: x0..2, v3..5, q6..9 (w,x,y,z), W10..12.
 // gt points at the vehicle's group entry (LDS).  Returns the number of
 // rotors whose raw command fell outside [u_min, u_max]; fills W (commanded
 // and applied wrench) and u (clamped thrusts, zero-padded) when requested.
-template <int NR, bool WANT_W, bool WANT_U>
-AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
-                float dt, float g, Wrench* W, float* u_out) {
+// With GRAD the same forward computation is followed by its hand-written
+// reverse: the loss gradient at the post-step state is added to adj->lam,
+// which is then pulled back through integration, allocation (clamp
+// subgradient 1 inside [u_min, u_max], bounds included), the moment law,
+// the tilt extraction, the yaw readout and R(q).
+template <int NR, bool WANT_W, bool WANT_U, bool GRAD>
+AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
+                     float dt, float g, Wrench* W, float* u_out, Adj* adj) {
     const float qw = s[6], qx = s[7], qy = s[8], qz = s[9];
     // ---- R(q), unit-norm form --------------------------------------------
     const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
@@ -239,11 +253,13 @@ AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __re
     const float a1 = M0 * P.inv_arm, a2 = M1 * P.inv_arm;
     float fa = 0.0f, Ma0 = 0.0f, Ma1 = 0.0f, Ma2 = 0.0f;
     int nsat = 0;
+    float raws[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
         const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
         const float raw = ap.x * f + ap.y * a1 + ap.z * a2 + ap.w * M2;
+        raws[r] = raw;
         const bool act = r < P.nr;
         const float u = act ? fminf(fmaxf(raw, P.umin), P.umax) : 0.0f;
         nsat += (act && (raw < P.umin || raw > P.umax)) ? 1 : 0;
@@ -282,7 +298,183 @@ AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __re
     const float tw = qw + hd * dqw, tx = qx + hd * dqx, ty = qy + hd * dqy, tz = qz + hd * dqz;
     const float iq = rsqrtf(tw * tw + tx * tx + ty * ty + tz * tz);
     s[6] = tw * iq; s[7] = tx * iq; s[8] = ty * iq; s[9] = tz * iq;
+
+    if constexpr (GRAD) {
+        float* L = adj->lam;
+        float* gb = adj->gb;
+        // loss at the post-step state
+        L[0] += 2.0f * (s[0] - adj->gx);
+        L[1] += 2.0f * (s[1] - adj->gy);
+        L[2] += 2.0f * (s[2] - adj->gz);
+        L[10] += 2.0f * adj->w_omega * nw0;
+        L[11] += 2.0f * adj->w_omega * nw1;
+        L[12] += 2.0f * adj->w_omega * nw2;
+
+        // ---- quaternion update: q+ = (q + hd q (x) (0, w+)) / |.| ----------
+        const float nq0 = s[6], nq1 = s[7], nq2 = s[8], nq3 = s[9];
+        const float dot = nq0 * L[6] + nq1 * L[7] + nq2 * L[8] + nq3 * L[9];
+        const float bt0 = iq * (L[6] - nq0 * dot), bt1 = iq * (L[7] - nq1 * dot);
+        const float bt2 = iq * (L[8] - nq2 * dot), bt3 = iq * (L[9] - nq3 * dot);
+        const float bdw = hd * bt0, bdx = hd * bt1, bdy = hd * bt2, bdz = hd * bt3;
+        float bqw = bt0 + bdx * nw0 + bdy * nw1 + bdz * nw2;
+        float bqx = bt1 - bdw * nw0 - bdy * nw2 + bdz * nw1;
+        float bqy = bt2 - bdw * nw1 + bdx * nw2 - bdz * nw0;
+        float bqz = bt3 - bdw * nw2 - bdx * nw1 + bdy * nw0;
+        const float bnw0 = L[10] - bdw * qx + bdx * qw + bdy * qz - bdz * qy;
+        const float bnw1 = L[11] - bdw * qy - bdx * qz + bdy * qw + bdz * qx;
+        const float bnw2 = L[12] - bdw * qz + bdx * qy - bdy * qx + bdz * qw;
+
+        // ---- rate update: w+ = w + dt J^-1 (M' - w x J w) -----------------
+        float bw0 = bnw0, bw1 = bnw1, bw2 = bnw2;
+        const float bMa0 = dt * (P.Ji0 * bnw0), bMa1 = dt * (P.Ji1 * bnw1), bMa2 = dt * (P.Ji2 * bnw2);
+        float bgy0 = -bMa0, bgy1 = -bMa1, bgy2 = -bMa2;
+
+        // ---- translation: x+ = x + dt v+, v+ = v + dt (acc b3 - g e3) ------
+        const float bnv0 = L[3] + dt * L[0], bnv1 = L[4] + dt * L[1], bnv2 = L[5] + dt * L[2];
+        float bx0 = L[0], bx1 = L[1], bx2 = L[2];
+        float bv0 = bnv0, bv1 = bnv1, bv2 = bnv2;
+        const float bacc = dt * (bnv0 * R02 + bnv1 * R12 + bnv2 * R22);
+        float bR00 = 0.0f, bR01 = 0.0f, bR10 = 0.0f, bR11 = 0.0f, bR20 = 0.0f, bR21 = 0.0f;
+        float bR02 = dt * (acc * bnv0), bR12 = dt * (acc * bnv1), bR22 = dt * (acc * bnv2);
+        const float bfa = bacc * P.inv_m;
+
+        // ---- allocation and clamp ----------------------------------------
+        const float bS1 = P.arm * bMa0, bS2 = P.arm * bMa1;
+        float bf = 0.0f, ba1 = 0.0f, ba2 = 0.0f, bM2 = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
+            const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
+            const float bu = bfa * ac.x + bS1 * ac.y + bS2 * ac.z + bMa2 * ac.w;
+            const bool pass = r < P.nr && raws[r] >= P.umin && raws[r] <= P.umax;
+            const float braw = pass ? bu : 0.0f;
+            bf += braw * ap.x;
+            ba1 += braw * ap.y;
+            ba2 += braw * ap.z;
+            bM2 += braw * ap.w;
+        }
+        float bM0 = ba1 * P.inv_arm, bM1 = ba2 * P.inv_arm;
+        const bool ctl = m0 || m1 || m2;       // M depends on the state
+        const bool frc = m0 || m1;             // f and the tilt depend on the state
+        bM0 = ctl ? bM0 : 0.0f;
+        bM1 = ctl ? bM1 : 0.0f;
+        bM2 = ctl ? bM2 : 0.0f;
+        bf = frc ? bf : 0.0f;
+
+        // ---- moment law, eq. (5) -------------------------------------------
+        gb[4] -= bM0 * eR0; gb[5] -= bM1 * eR1; gb[6] -= bM2 * eR2;
+        gb[7] -= bM0 * eW0; gb[8] -= bM1 * eW1; gb[9] -= bM2 * eW2;
+        const float beR0 = -P.kR0 * bM0, beR1 = -P.kR1 * bM1, beR2 = -P.kR2 * bM2;
+        const float beW0 = -P.kW0 * bM0, beW1 = -P.kW1 * bM1, beW2 = -P.kW2 * bM2;
+        bgy0 += bM0; bgy1 += bM1; bgy2 += bM2;
+        bw0 += -bgy1 * JW2 + bgy2 * JW1;
+        bw1 += bgy0 * JW2 - bgy2 * JW0;
+        bw2 += -bgy0 * JW1 + bgy1 * JW0;
+        const float bJW0 = bgy1 * w2 - bgy2 * w1, bJW1 = bgy2 * w0 - bgy0 * w2, bJW2 = bgy0 * w1 - bgy1 * w0;
+        bw0 += P.J0 * bJW0 + beW0;
+        bw1 += P.J1 * bJW1 + beW1;
+        bw2 += P.J2 * bJW2 + beW2;
+        bR20 -= psidot * beW0; bR21 -= psidot * beW1; bR22 -= psidot * beW2;
+
+        // ---- attitude error, eq. (3) -------------------------------------
+        const float bE21 = 0.5f * beR0, bE12 = -0.5f * beR0;
+        const float bE02 = 0.5f * beR1, bE20 = -0.5f * beR1;
+        const float bE10 = 0.5f * beR2, bE01 = -0.5f * beR2;
+        float bP00 = 0.0f, bP01 = 0.0f, bP02 = 0.0f, bP10 = 0.0f, bP11 = 0.0f, bP12 = 0.0f;
+        float bP20 = 0.0f, bP21 = 0.0f, bP22 = 0.0f;
+        float bT01 = 0.0f, bT02 = 0.0f, bT21 = 0.0f, bT22 = 0.0f;
+        float bcth = 0.0f, bsth = 0.0f, bcph = 0.0f, bsph = 0.0f;
+        bT02 += bE21 * P01; bP01 += bE21 * T02; bsph -= bE21 * P11; bP11 -= bE21 * sph;
+        bT22 += bE21 * P21; bP21 += bE21 * T22;
+        bT01 += bE12 * P02; bP02 += bE12 * T01; bcph += bE12 * P12; bP12 += bE12 * cph;
+        bT21 += bE12 * P22; bP22 += bE12 * T21;
+        bcth += bE02 * P02; bP02 += bE02 * cth; bsth -= bE02 * P22; bP22 -= bE02 * sth;
+        bT02 += bE20 * P00; bP00 += bE20 * T02; bsph -= bE20 * P10; bP10 -= bE20 * sph;
+        bT22 += bE20 * P20; bP20 += bE20 * T22;
+        bT01 += bE10 * P00; bP00 += bE10 * T01; bcph += bE10 * P10; bP10 += bE10 * cph;
+        bT21 += bE10 * P20; bP20 += bE10 * T21;
+        bcth += bE01 * P01; bP01 += bE01 * cth; bsth -= bE01 * P21; bP21 -= bE01 * sth;
+        bsth += bT01 * sph + bT02 * cph;
+        bsph += bT01 * sth + bT21 * cth;
+        bcph += bT02 * sth + bT22 * cth;
+        bcth += bT21 * sph + bT22 * cph;
+
+        // ---- thrust projection ---------------------------------------------
+        float bFx = bf * P02, bFy = bf * P12, bFz = bf * P22;
+        bP02 += bf * Fx; bP12 += bf * Fy; bP22 += bf * Fz;
+
+        // ---- P = R_z(psi_ref)^T R -------------------------------------------
+        bR00 += cr * bP00 - sr * bP10; bR10 += sr * bP00 + cr * bP10; bR20 += bP20;
+        bR01 += cr * bP01 - sr * bP11; bR11 += sr * bP01 + cr * bP11; bR21 += bP21;
+        bR02 += cr * bP02 - sr * bP12; bR12 += sr * bP02 + cr * bP12; bR22 += bP22;
+        float bcr = bP00 * R00 + bP10 * R10 + bP01 * R01 + bP11 * R11 + bP02 * R02 + bP12 * R12;
+        float bsr = bP00 * R10 - bP10 * R00 + bP01 * R11 - bP11 * R01 + bP02 * R12 - bP12 * R02;
+
+        // ---- tilt extraction, eqs. (8)-(9) ----------------------------------
+        if (hok) {
+            const float ih3 = ih * ih * ih;
+            const float D = (bcth * Fx - bsth * Fz) * ih3;
+            bFx -= Fz * D;
+            bFz += Fx * D;
+            const float inn3 = inn * inn * inn;
+            const float Gq = (bcph * (Fy * Fy) * ih + bsph * Fy) * inn3;
+            bFx += Fx * Gq;
+            bFz += Fz * Gq;
+            bFy -= (bcph * hh * Fy + bsph * h2) * inn3;
+        }
+        bFx = frc ? bFx : 0.0f;
+        bFy = frc ? bFy : 0.0f;
+        bFz = frc ? bFz : 0.0f;
+
+        // ---- commanded force: F = m a, a = kx e + kv (v_d - v_V) ------------
+        const float bax = P.m * bFx, bay = P.m * bFy, baz = P.m * bFz;
+        gb[0] += bax * ex + bay * ey;
+        gb[1] += baz * ez;
+        gb[2] += bax * wvx + bay * wvy;
+        gb[3] += baz * wvz;
+        const float bex = P.kx_xy * bax, bey = P.kx_xy * bay, bez = P.kx_z * baz;
+        const float bvVx = -(P.kv_xy * bax), bvVy = -(P.kv_xy * bay);
+        bv2 -= P.kv_z * baz;
+        if (m0) {
+            bx0 -= cr * bex - sr * bey;
+            bx1 -= sr * bex + cr * bey;
+            bx2 -= bez;
+            bcr += bex * dxE + bey * dyE;
+            bsr += bex * dyE - bey * dxE;
+        }
+        bv0 += cr * bvVx - sr * bvVy;
+        bv1 += sr * bvVx + cr * bvVy;
+        bcr += bvVx * vx + bvVy * vy;
+        bsr += bvVx * vy - bvVy * vx;
+
+        // ---- yaw readout (reference frame of velocity / attitude modes) -----
+        if (!m0 && yok) {
+            const float D2 = (bcr * R10 - bsr * R00) * (ir * ir * ir);
+            bR00 += R10 * D2;
+            bR10 -= R00 * D2;
+        }
+
+        // ---- R(q) -----------------------------------------------------------
+        const float bxx = -2.0f * (bR11 + bR22), byy = -2.0f * (bR00 + bR22), bzz = -2.0f * (bR00 + bR11);
+        const float bxy = 2.0f * (bR01 + bR10), bxz = 2.0f * (bR02 + bR20), byz = 2.0f * (bR12 + bR21);
+        const float bwx = 2.0f * (bR21 - bR12), bwy = 2.0f * (bR02 - bR20), bwz = 2.0f * (bR10 - bR01);
+        bqx += 2.0f * qx * bxx + qy * bxy + qz * bxz + qw * bwx;
+        bqy += 2.0f * qy * byy + qx * bxy + qz * byz + qw * bwy;
+        bqz += 2.0f * qz * bzz + qx * bxz + qy * byz + qw * bwz;
+        bqw += qx * bwx + qy * bwy + qz * bwz;
+
+        L[0] = bx0; L[1] = bx1; L[2] = bx2;
+        L[3] = bv0; L[4] = bv1; L[5] = bv2;
+        L[6] = bqw; L[7] = bqx; L[8] = bqy; L[9] = bqz;
+        L[10] = bw0; L[11] = bw1; L[12] = bw2;
+    }
     return nsat;
+}
+
+template <int NR, bool WANT_W, bool WANT_U>
+AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
+                float dt, float g, Wrench* W, float* u_out) {
+    return step_core<NR, WANT_W, WANT_U, false>(s, C, P, gt, dt, g, W, u_out, nullptr);
 }
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
