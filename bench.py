@@ -184,6 +184,7 @@ def main():
 
     import torch
     import workloads
+    from paper_2305_16510_amd import probe
     from paper_2305_16510_amd.sim import Sim
 
     if not torch.cuda.is_available():
@@ -304,13 +305,18 @@ def main():
     if args.copy_calib_mib:
         # a plain device copy of known size: calibrates the HBM byte counters
         nb = args.copy_calib_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        sync()
-        out["copy_calibration"] = {"bytes_read": nb, "bytes_written": nb, "dispatches": 3}
-        del src, dst
+        probe.copy_once(nb)
+        out["copy_calibration"] = {"kernel": "k_copy (agp_copy)", "bytes_read": nb, "bytes_written": nb,
+                                   "dispatches": 3}
+    if not args.no_extras:
+        fma = probe.valu_fma_peak()
+        cbw = probe.copy_bandwidth()
+        out["measured_peaks"] = {"fp32_fma_lane_ops_per_s": fma, "fp32_fma_tflops": 2 * fma / 1e12,
+                                 "copy_GBs": cbw / 1e9}
+        out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / (2 * fma / 1e12)
+        if per_step:
+            per_step["roofline"]["frac_of_measured_copy"] = per_step["roofline"]["achieved"] / (cbw / 1e9)
+        log(f"measured peaks: FP32 FMA {2 * fma / 1e12:.1f} TFLOP/s, copy {cbw / 1e9:.0f} GB/s")
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, args.cpu_steps)

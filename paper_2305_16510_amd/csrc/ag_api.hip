@@ -442,7 +442,7 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
     for (auto& g : h->groups) maxr = std::max(maxr, g.n_rotors);
     bool uniform = true;
     for (auto& g : h->groups) uniform = uniform && g.n_rotors == h->groups[0].n_rotors;
-    h->nr_class = uniform ? h->groups[0].n_rotors : 8;
+    h->nr_class = uniform ? h->groups[0].n_rotors : 0;   // 0: mixed rotor counts
     (void)maxr;
     h->vp = cfg->vparams != nullptr;
     h->reset_on = cfg->auto_reset != 0 && cfg->reset_prob > 0.0f;

@@ -146,15 +146,27 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
         }
 
         Wrench W[VPL];
-        float u[VPL][NR];
+        float u[VPL][RotorClass<NR>::NR];
+        uint4 mw[VPL];
+        long long mblk = -1;
         for (int st = 0; st < K; ++st) {
             const bool out_step = want_out && st == K - 1;
+            if constexpr (RESET) {
+                // reset words of four consecutive steps come from one Philox call
+                const long long tb = (tbase + st) >> 2;
+                if (tb != mblk) {
+                    mblk = tb;
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v)
+                        mw[v] = mask_block(a.index_base + (uint32_t)idx[v], (uint64_t)tb, a.key0, a.key1);
+                }
+            }
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
                 if (!act[v]) continue;
                 if constexpr (RESET) {
                     const uint32_t gi = a.index_base + (uint32_t)idx[v];
-                    if (reset_mask(gi, tbase + st, a.key0, a.key1, a.thr)) {
+                    if (mask_hit(mw[v], tbase + st, a.thr)) {
                         float gx, gy, gz;
                         redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
                         if (C[v].mode == 0) derive_cmd(C[v], 0, gx, gy, gz, 0.0f);
@@ -197,7 +209,7 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
                 }
                 if (a.rotor_out) {
 #pragma unroll
-                    for (int r = 0; r < 8; ++r) a.rotor_out[r * ld + i] = r < NR ? u[v][r] : 0.0f;
+                    for (int r = 0; r < 8; ++r) a.rotor_out[r * ld + i] = r < RotorClass<NR>::NR ? u[v][r] : 0.0f;
                 }
             }
             bool finite = true;
@@ -379,7 +391,8 @@ const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_ste
     switch (nr_class) {
         case 4: return pick_nr<4>(vp, reset, vpl, one_step);
         case 6: return pick_nr<6>(vp, reset, vpl, one_step);
-        default: return pick_nr<8>(vp, reset, vpl, one_step);
+        case 8: return pick_nr<8>(vp, reset, vpl, one_step);
+        default: return pick_nr<0>(vp, reset, vpl, one_step);
     }
 }
 

@@ -139,7 +139,8 @@ const void* rollout_fwd_kernel(int nr_class) {
     switch (nr_class) {
         case 4: return reinterpret_cast<const void*>(&k_rollout_fwd<4>);
         case 6: return reinterpret_cast<const void*>(&k_rollout_fwd<6>);
-        default: return reinterpret_cast<const void*>(&k_rollout_fwd<8>);
+        case 8: return reinterpret_cast<const void*>(&k_rollout_fwd<8>);
+        default: return reinterpret_cast<const void*>(&k_rollout_fwd<0>);
     }
 }
 
@@ -147,7 +148,8 @@ const void* rollout_adj_kernel(int nr_class) {
     switch (nr_class) {
         case 4: return reinterpret_cast<const void*>(&k_rollout_adj<4>);
         case 6: return reinterpret_cast<const void*>(&k_rollout_adj<6>);
-        default: return reinterpret_cast<const void*>(&k_rollout_adj<8>);
+        case 8: return reinterpret_cast<const void*>(&k_rollout_adj<8>);
+        default: return reinterpret_cast<const void*>(&k_rollout_adj<0>);
     }
 }
 

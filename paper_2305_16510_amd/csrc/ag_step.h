@@ -122,6 +122,19 @@ AG_DEV void load_params(Params& P, const float* __restrict__ gt, const float* __
     }
 }
 
+// Reciprocal square root as the single hardware instruction (1 ulp); every
+// argument here is a sum of squares of order one to a few hundred, never a
+// denormal, so the denormal-range rescaling of rsqrtf is not needed.
+AG_DEV float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Rotor-count class of a kernel: 4, 6 or 8 when every group of the launch
+// has that many rotors, 0 for a mix (8 slots, inactive slots masked).
+template <int NRC>
+struct RotorClass {
+    static constexpr int NR = NRC == 0 ? 8 : NRC;
+    static constexpr bool MIXED = NRC == 0;
+};
+
 AG_DEV void derive_cmd(Cmd& C, int mode, float t0, float t1, float t2, float t3) {
     C.mode = mode;
     C.t0 = t0; C.t1 = t1; C.t2 = t2; C.t3 = t3;
@@ -150,9 +163,11 @@ struct Adj {
 // which is then pulled back through integration, allocation (clamp
 // subgradient 1 inside [u_min, u_max], bounds included), the moment law,
 // the tilt extraction, the yaw readout and R(q).
-template <int NR, bool WANT_W, bool WANT_U, bool GRAD>
+template <int NRC, bool WANT_W, bool WANT_U, bool GRAD>
 AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
                      float dt, float g, Wrench* W, float* u_out, Adj* adj) {
+    constexpr int NR = RotorClass<NRC>::NR;
+    constexpr bool MIXED = RotorClass<NRC>::MIXED;
     const float qw = s[6], qx = s[7], qy = s[8], qz = s[9];
     // ---- R(q), unit-norm form --------------------------------------------
     const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
@@ -165,7 +180,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     // ---- current yaw (Z-Y-X), trig-free -----------------------------------
     const float r2 = R00 * R00 + R10 * R10;
     const bool yok = r2 > 0.0f;
-    const float ir = rsqrtf(r2);
+    const float ir = rsq(r2);
     const float cpsi = yok ? R00 * ir : 1.0f;
     const float spsi = yok ? R10 * ir : 0.0f;
 
@@ -196,7 +211,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float h2 = Fx * Fx + Fz * Fz;
     const float n2 = h2 + Fy * Fy;
     const bool hok = h2 > 0.0f, nok = n2 > 0.0f;
-    const float ih = rsqrtf(h2), inn = rsqrtf(n2);
+    const float ih = rsq(h2), inn = rsq(n2);
     const float hh = hok ? h2 * ih : 0.0f;
     float cth = hok ? Fz * ih : 1.0f;
     float sth = hok ? Fx * ih : 0.0f;
@@ -251,7 +266,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
 
     // ---- allocation and clamping ------------------------------------------
     const float a1 = M0 * P.inv_arm, a2 = M1 * P.inv_arm;
-    float fa = 0.0f, Ma0 = 0.0f, Ma1 = 0.0f, Ma2 = 0.0f;
+    float fa, Ma0, Ma1, Ma2;
     int nsat = 0;
     float raws[NR];
 #pragma unroll
@@ -260,13 +275,23 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
         const float raw = ap.x * f + ap.y * a1 + ap.z * a2 + ap.w * M2;
         raws[r] = raw;
-        const bool act = r < P.nr;
-        const float u = act ? fminf(fmaxf(raw, P.umin), P.umax) : 0.0f;
-        nsat += (act && (raw < P.umin || raw > P.umax)) ? 1 : 0;
-        fa += u * ac.x;
-        Ma0 += u * ac.y;
-        Ma1 += u * ac.z;
-        Ma2 += u * ac.w;
+        // clamp to [u_min, u_max] as one median-of-three; in a mixed launch the
+        // slots beyond the group's rotor count are masked to zero
+        const bool act = MIXED ? r < P.nr : true;
+        float u = __builtin_amdgcn_fmed3f(raw, P.umin, P.umax);
+        if constexpr (MIXED) u = act ? u : 0.0f;
+        nsat += (int)(act & ((raw < P.umin) | (raw > P.umax)));
+        if (r == 0) {
+            fa = u * ac.x;
+            Ma0 = u * ac.y;
+            Ma1 = u * ac.z;
+            Ma2 = u * ac.w;
+        } else {
+            fa += u * ac.x;
+            Ma0 += u * ac.y;
+            Ma1 += u * ac.z;
+            Ma2 += u * ac.w;
+        }
         if constexpr (WANT_U) u_out[r] = u;
     }
     Ma0 *= P.arm;
@@ -296,7 +321,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float dqy = qw * nw1 + (qz * nw0 - qx * nw2);
     const float dqz = qw * nw2 + (qx * nw1 - qy * nw0);
     const float tw = qw + hd * dqw, tx = qx + hd * dqx, ty = qy + hd * dqy, tz = qz + hd * dqz;
-    const float iq = rsqrtf(tw * tw + tx * tx + ty * ty + tz * tz);
+    const float iq = rsq(tw * tw + tx * tx + ty * ty + tz * tz);
     s[6] = tw * iq; s[7] = tx * iq; s[8] = ty * iq; s[9] = tz * iq;
 
     if constexpr (GRAD) {
@@ -346,7 +371,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
             const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
             const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
             const float bu = bfa * ac.x + bS1 * ac.y + bS2 * ac.z + bMa2 * ac.w;
-            const bool pass = r < P.nr && raws[r] >= P.umin && raws[r] <= P.umax;
+            const bool pass = (MIXED ? r < P.nr : true) & (raws[r] >= P.umin) & (raws[r] <= P.umax);
             const float braw = pass ? bu : 0.0f;
             bf += braw * ap.x;
             ba1 += braw * ap.y;
@@ -471,10 +496,10 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     return nsat;
 }
 
-template <int NR, bool WANT_W, bool WANT_U>
+template <int NRC, bool WANT_W, bool WANT_U>
 AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
                 float dt, float g, Wrench* W, float* u_out) {
-    return step_core<NR, WANT_W, WANT_U, false>(s, C, P, gt, dt, g, W, u_out, nullptr);
+    return step_core<NRC, WANT_W, WANT_U, false>(s, C, P, gt, dt, g, W, u_out, nullptr);
 }
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
@@ -497,12 +522,20 @@ AG_DEV uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 
 // Reset decision of global vehicle gi before global step t: word (t mod 4) of
 // Philox(counter = (gi, lo(t/4), hi(t/4), TAG_MASK)) compared with thr.
-AG_DEV bool reset_mask(uint32_t gi, int64_t t, uint32_t k0, uint32_t k1, uint64_t thr) {
-    const uint64_t tb = (uint64_t)t >> 2;
-    const uint4 w = philox(make_uint4(gi, (uint32_t)tb, (uint32_t)(tb >> 32), TAG_MASK), k0, k1);
+// One Philox call serves four consecutive steps: mask_block gives the words of
+// steps 4 tb .. 4 tb + 3, mask_hit picks the word of step t.
+AG_DEV uint4 mask_block(uint32_t gi, uint64_t tb, uint32_t k0, uint32_t k1) {
+    return philox(make_uint4(gi, (uint32_t)tb, (uint32_t)(tb >> 32), TAG_MASK), k0, k1);
+}
+
+AG_DEV bool mask_hit(uint4 w, int64_t t, uint64_t thr) {
     const int sel = (int)(t & 3);
     const uint32_t word = sel == 0 ? w.x : (sel == 1 ? w.y : (sel == 2 ? w.z : w.w));
     return (uint64_t)word < thr;
+}
+
+AG_DEV bool reset_mask(uint32_t gi, int64_t t, uint32_t k0, uint32_t k1, uint64_t thr) {
+    return mask_hit(mask_block(gi, (uint64_t)t >> 2, k0, k1), t, thr);
 }
 
 AG_DEV float u24(uint32_t w) { return (float)(w >> 8) * 5.9604644775390625e-8f; }   // 2^-24
