@@ -288,7 +288,8 @@ std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
     long long grid = (one || e.grid == 0) ? ntiles : std::min<long long>(e.grid, ntiles);
     if (grid > h->L.nslots) grid = h->L.nslots;
     if (grid > 2147483647LL) return "grid too large";
-    s.fn = step_kernel(h->nr_class, h->vp, h->reset_on, vpl, one);
+    const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
+    s.fn = step_kernel(h->nr_class, h->vp, h->reset_on, vpl, one, obs);
     s.grid = dim3((unsigned)grid);
     s.block = dim3((unsigned)e.block);
     s.span = span;

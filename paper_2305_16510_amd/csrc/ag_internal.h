@@ -90,7 +90,7 @@ constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
 
 // Kernel lookup (defined in ag_kernels.hip).  nr_class: 4, 6 or 8 rotors in
 // every group, or 0 for a launch mixing rotor counts.
-const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step);
+const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs);
 const void* fold_kernel();
 const void* advance_kernel();
 const void* set_step_kernel();

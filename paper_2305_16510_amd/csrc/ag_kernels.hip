@@ -8,7 +8,7 @@
 // inertia, default gains); lanes find their group by scanning the staged
 // group offsets.
 //
-// k_step<NR, VP, RESET, VPL, ONE> is both the per-step kernel (ONE: one step
+// k_step<NR, VP, RESET, VPL, ONE, OBS> is both the per-step kernel (ONE: one step
 // per launch, one tile per block) and the fused kernel (k steps per launch
 // with the state held in registers, VPL vehicles per lane, grid-stride loop
 // over tiles).  A grid that is a multiple of 8 keeps each tile on the same
@@ -96,7 +96,7 @@ __device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, l
     }
 }
 
-template <int NR, bool VP, bool RESET, int VPL, bool ONE>
+template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS>
 __global__ __launch_bounds__(512) void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
@@ -109,7 +109,9 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
     const long long tbase = a.d_step ? (*a.d_step + a.t_off) : a.t0;
     const int K = ONE ? 1 : a.k;
     const long long ld = a.ld;
-    const bool want_out = a.wrench_out != nullptr || a.rotor_out != nullptr;
+    // OBS: some observer (wrench or rotor outputs, flags, statistics) is bound;
+    // without one the saturation and reset counting compiles away.
+    const bool want_out = OBS && (a.wrench_out != nullptr || a.rotor_out != nullptr);
 
     long long c_sat = 0, c_res = 0, c_nonf = 0, c_fin = 0, c_pos = 0;
     double s_err = 0.0, s_w = 0.0;
@@ -171,14 +173,16 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
                         redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
                         if (C[v].mode == 0) derive_cmd(C[v], 0, gx, gy, gz, 0.0f);
                         did_reset[v] = true;
-                        ++c_res;
+                        if constexpr (OBS) ++c_res;
                     }
                 }
                 int ns;
                 if (out_step) ns = step<NR, true, true>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
                 else ns = step<NR, false, false>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
-                c_sat += ns;
-                sat_last[v] = ns;
+                if constexpr (OBS) {
+                    c_sat += ns;
+                    sat_last[v] = ns;
+                }
             }
         }
 
@@ -215,13 +219,13 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
             bool finite = true;
 #pragma unroll
             for (int r = 0; r < 13; ++r) finite = finite && isfinite(s[v][r]);
-            if (a.flags_out) {
+            if (OBS && a.flags_out) {
                 uint8_t fl = (finite ? 0 : AG_FLAG_NONFINITE) | (sat_last[v] ? AG_FLAG_SATURATED : 0) |
                              (did_reset[v] ? AG_FLAG_RESET : 0);
                 if (a.flags_accumulate) fl |= (a.flags_out[i] & AG_FLAG_RESET);
                 a.flags_out[i] = fl;
             }
-            if (a.slots) {
+            if (OBS && a.slots) {
                 if (finite) {
                     ++c_fin;
                     s_w += (double)sqrtf(s[v][10] * s[v][10] + s[v][11] * s[v][11] + s[v][12] * s[v][12]);
@@ -237,7 +241,9 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
         }
         __syncthreads();   // LDS is restaged for the next tile
     }
-    if (a.slots) block_stats(a.slots, c_sat, c_res, c_nonf, c_fin, c_pos, s_err, s_w);
+    if constexpr (OBS) {
+        if (a.slots) block_stats(a.slots, c_sat, c_res, c_nonf, c_fin, c_pos, s_err, s_w);
+    }
 }
 
 // ---- statistics fold: slots -> cumulative accumulator (one block) ---------
@@ -374,25 +380,30 @@ __global__ __launch_bounds__(kResetBlock) void k_reset_scatter(ScatterArgs a) {
 }
 
 // ---- kernel lookup ---------------------------------------------------------
+template <int NR, bool VP, bool RESET, bool OBS>
+static const void* pick_obs(int vpl, bool one) {
+    if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, true, OBS>);
+    if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 2, false, OBS>);
+    return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, false, OBS>);
+}
+
 template <int NR, bool VP, bool RESET>
-static const void* pick_step(int vpl, bool one) {
-    if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, true>);
-    if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 2, false>);
-    return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, false>);
+static const void* pick_step(int vpl, bool one, bool obs) {
+    return obs ? pick_obs<NR, VP, RESET, true>(vpl, one) : pick_obs<NR, VP, RESET, false>(vpl, one);
 }
 
 template <int NR>
-static const void* pick_nr(bool vp, bool reset, int vpl, bool one) {
-    if (vp) return reset ? pick_step<NR, true, true>(vpl, one) : pick_step<NR, true, false>(vpl, one);
-    return reset ? pick_step<NR, false, true>(vpl, one) : pick_step<NR, false, false>(vpl, one);
+static const void* pick_nr(bool vp, bool reset, int vpl, bool one, bool obs) {
+    if (vp) return reset ? pick_step<NR, true, true>(vpl, one, obs) : pick_step<NR, true, false>(vpl, one, obs);
+    return reset ? pick_step<NR, false, true>(vpl, one, obs) : pick_step<NR, false, false>(vpl, one, obs);
 }
 
-const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step) {
+const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs) {
     switch (nr_class) {
-        case 4: return pick_nr<4>(vp, reset, vpl, one_step);
-        case 6: return pick_nr<6>(vp, reset, vpl, one_step);
-        case 8: return pick_nr<8>(vp, reset, vpl, one_step);
-        default: return pick_nr<0>(vp, reset, vpl, one_step);
+        case 4: return pick_nr<4>(vp, reset, vpl, one_step, obs);
+        case 6: return pick_nr<6>(vp, reset, vpl, one_step, obs);
+        case 8: return pick_nr<8>(vp, reset, vpl, one_step, obs);
+        default: return pick_nr<0>(vp, reset, vpl, one_step, obs);
     }
 }
 

@@ -121,10 +121,22 @@ __global__ __launch_bounds__(256) void k_rollout_adj(RolloutArgs a) {
             for (int r = 0; r < 13; ++r) tp[r * n + i] = s[r];
             if (t + 1 < t1) step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
         }
-        for (int t = t1 - 1; t >= t0; --t) {
-            const float* tp = a.tape + (long long)(t - t0) * 13 * n;
+        // reverse sweep; the next (earlier) tape entry is loaded while the
+        // current step's reverse runs, hiding the load latency
+        float nxt[13];
+        {
+            const float* tp = a.tape + (long long)(t1 - 1 - t0) * 13 * n;
 #pragma unroll
-            for (int r = 0; r < 13; ++r) s[r] = tp[r * n + i];
+            for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
+        }
+        for (int t = t1 - 1; t >= t0; --t) {
+#pragma unroll
+            for (int r = 0; r < 13; ++r) s[r] = nxt[r];
+            if (t > t0) {
+                const float* tp = a.tape + (long long)(t - 1 - t0) * 13 * n;
+#pragma unroll
+                for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
+            }
             step_core<NR, false, false, true>(s, C, P, gt, a.dt, a.g, nullptr, nullptr, &A);
         }
     }
