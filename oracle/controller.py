@@ -81,12 +81,13 @@ def moment(e_R, e_W, Omega, J, kR, kW):
     return -kR * e_R - kW * e_W + torch.cross(Omega, J * Omega, dim=-1)
 
 
-def control(x, v, q, Omega, mode, target, fleet, g):
+def control(x, v, q, Omega, mode, target, fleet, g, traj=None):
     """One controller evaluation for every vehicle.
 
     x, v, Omega: [N,3]; q: [N,4] (w,x,y,z); mode: [N] integer; target: [N,4]
-    (the mode's 4-float command union); returns dict with the commanded
-    thrust ``f`` [N] and moment ``M`` [N,3] plus intermediates.
+    (the mode's 4-float command union); traj: optional [N,16] trajectory
+    rows of the tracking mode 4 (``oracle.lee``); returns dict with the
+    commanded thrust ``f`` [N] and moment ``M`` [N,3] plus intermediates.
     """
     mode = mode.to(torch.int64)
     R = quat_to_rot(q)
@@ -135,6 +136,14 @@ def control(x, v, q, Omega, mode, target, fleet, g):
     f = torch.where(is3, target[:, 0], f)
     M = torch.where(is3.unsqueeze(-1), target[:, 1:4], M)
     known = is0 | is1 | is2 | is3
+    if traj is not None:
+        from .lee import MODE_TRACK, lee_tracking
+        is4 = mode == MODE_TRACK
+        lt = lee_tracking(x, v, q, Omega, traj, fleet, g)
+        f = torch.where(is4, lt["f"], f)
+        M = torch.where(is4.unsqueeze(-1), lt["M"], M)
+        R_d = torch.where(is4[:, None, None], lt["R_d"], R_d)
+        known = known | is4
     f = torch.where(known, f, zero)
     M = torch.where(known.unsqueeze(-1), M, torch.zeros_like(M))
     return {"f": f, "M": M, "R": R, "R_d": R_d, "Omega_d": Omega_d, "e_R": e_R,

@@ -25,25 +25,26 @@ def split(state):
     return state[:, 0:3], state[:, 3:6], state[:, 6:10], state[:, 10:13]
 
 
-def step(state, mode, target, fleet, dt, g, tabs=None):
+def step(state, mode, target, fleet, dt, g, tabs=None, traj=None):
     """state [N,13], mode [N], target [N,4] -> (next state [N,13], info)."""
     x, v, q, W = split(state)
-    c = control(x, v, q, W, mode, target, fleet, g)
+    c = control(x, v, q, W, mode, target, fleet, g, traj)
     u, f_app, M_app, raw = allocation.allocate(c["f"], c["M"], fleet, tabs)
     xn, vn, qn, Wn = integrate(x, v, q, W, f_app, M_app, fleet, dt, g)
     info = {"f": c["f"], "M": c["M"], "f_app": f_app, "M_app": M_app, "u": u, "u_raw": raw}
     return torch.cat([xn, vn, qn, Wn], -1), info
 
 
-def rollout(state0, mode, target, fleet, dt, g, steps, keep_states=False):
+def rollout(state0, mode, target, fleet, dt, g, steps, keep_states=False, traj=None):
     """Run ``steps`` steps; returns (final state, list of states or None, saturated
     rotor-step count per vehicle)."""
     tabs = allocation.tables(fleet)
     s = state0
     states = [] if keep_states else None
     sat = torch.zeros(state0.shape[0], dtype=torch.int64)
-    for _ in range(steps):
-        s, info = step(s, mode, target, fleet, dt, g, tabs)
+    for k in range(steps):
+        tr = traj(k) if callable(traj) else traj      # traj may be a function of the step
+        s, info = step(s, mode, target, fleet, dt, g, tabs, tr)
         sat += allocation.saturated_count(info["u_raw"].detach(), fleet)
         if keep_states:
             states.append(s)
