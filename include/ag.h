@@ -68,7 +68,16 @@ typedef enum {
     AG_E_UNSUPPORTED = 5  /* feature combination not implemented */
 } ag_status;
 
-enum { AG_MODE_POSITION = 0, AG_MODE_VELOCITY = 1, AG_MODE_ATTITUDE = 2, AG_MODE_WRENCH = 3 };
+/* Mode 4 (AG_MODE_TRACK) is the full geometric tracking law of Lee et al.,
+ * the reference the paper adapts (Sec. IV): desired frame from the force
+ * direction and a heading b1d = (cos psi_d, sin psi_d, 0), and the moment's
+ * feed-forward term -J (hat(Omega) R^T R_d Omega_d - R^T R_d dOmega_d) that the
+ * paper drops after eq. (5) restored.  It reads cfg.traj (16 rows per vehicle:
+ * x_d(3), v_d(3), a_d(3), psi_d, Omega_d(3), dOmega_d(3)); without cfg.traj a
+ * mode-4 vehicle gets a zero wrench.  Commands and trajectory rows are read
+ * once per launch and held for the steps of that launch. */
+#define AG_TRAJ_DIM 16
+enum { AG_MODE_POSITION = 0, AG_MODE_VELOCITY = 1, AG_MODE_ATTITUDE = 2, AG_MODE_WRENCH = 3, AG_MODE_TRACK = 4 };
 
 /* Per-vehicle flag bits written to cfg.flags_out at the end of each ag_step. */
 enum { AG_FLAG_NONFINITE = 1, AG_FLAG_SATURATED = 2, AG_FLAG_RESET = 4 };
@@ -109,6 +118,7 @@ typedef struct {
     float reset_hi[3];
     int32_t collect_stats;  /* 1: ag_step accumulates the ag_stats counters and final-state sums */
     int32_t autotune_scratch;  /* 1: workspace holds scratch state so ag_autotune leaves results untouched */
+    const float* traj;      /* device [16][ld] or NULL: trajectory rows of mode 4 (see AG_MODE_TRACK) */
 } ag_config;
 
 /* Execution policy of ag_step.  kind 0: one launch of the per-step kernel per

@@ -244,6 +244,7 @@ StepArgs base_args(ag_handle h) {
     a.mode = h->cfg.mode;
     a.target = h->cfg.target;
     a.vparams = h->cfg.vparams;
+    a.traj = h->cfg.traj;
     a.gtab = h->gtab;
     a.goff = h->goff;
     a.wrench_out = h->cfg.wrench_out;
@@ -289,7 +290,9 @@ std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
     if (grid > h->L.nslots) grid = h->L.nslots;
     if (grid > 2147483647LL) return "grid too large";
     const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
-    s.fn = step_kernel(h->nr_class, h->vp, h->reset_on, vpl, one, obs);
+    const bool trk = h->cfg.traj != nullptr;
+    if (trk && vpl != 1) return "with a trajectory buffer exec.vpl must be 1";
+    s.fn = step_kernel(h->nr_class, h->vp, h->reset_on, vpl, one, obs, trk);
     s.grid = dim3((unsigned)grid);
     s.block = dim3((unsigned)e.block);
     s.span = span;
@@ -781,6 +784,7 @@ ag_status rollout_args(ag_handle h, const float* x0, int32_t n_steps, int32_t ck
                        size_t ws_bytes, RolloutArgs& a, LaunchShape& s) {
     if (n_steps < 1 || ckpt_every < 1) return set_err(h, AG_E_INVALID, "n_steps and ckpt_every must be >= 1");
     if (!h->cfg.vparams) return set_err(h, AG_E_UNSUPPORTED, "rollouts differentiate per-vehicle gains: vparams required");
+    if (h->cfg.traj) return set_err(h, AG_E_UNSUPPORTED, "rollouts of the tracking mode are not differentiated");
     if (!std::isfinite(w_omega)) return set_err(h, AG_E_INVALID, "w_omega must be finite");
     size_t need = 0;
     ag_status st = ag_rollout_workspace_size(h, n_steps, ckpt_every, &need);

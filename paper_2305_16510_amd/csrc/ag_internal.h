@@ -31,6 +31,7 @@ struct StepArgs {
     const int8_t* mode;        // [ld]
     float* target;             // [4][ld] (goals rewritten by resets)
     const float* vparams;      // [16][ld] or null
+    const float* traj;         // [16][ld] or null (tracking mode)
     const float* gtab;         // [n_groups][GSTRIDE]
     const int32_t* goff;       // [n_groups + 1]
     float* wrench_out;         // [8][ld] or null
@@ -90,7 +91,7 @@ constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
 
 // Kernel lookup (defined in ag_kernels.hip).  nr_class: 4, 6 or 8 rotors in
 // every group, or 0 for a launch mixing rotor counts.
-const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs);
+const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs, bool trk);
 const void* fold_kernel();
 const void* advance_kernel();
 const void* set_step_kernel();

@@ -8,7 +8,7 @@
 // inertia, default gains); lanes find their group by scanning the staged
 // group offsets.
 //
-// k_step<NR, VP, RESET, VPL, ONE, OBS> is both the per-step kernel (ONE: one step
+// k_step<NR, VP, RESET, VPL, ONE, OBS, TRK> is both the per-step kernel (ONE: one step
 // per launch, one tile per block) and the fused kernel (k steps per launch
 // with the state held in registers, VPL vehicles per lane, grid-stride loop
 // over tiles).  A grid that is a multiple of 8 keeps each tile on the same
@@ -96,7 +96,7 @@ __device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, l
     }
 }
 
-template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS>
+template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS, bool TRK>
 __global__ __launch_bounds__(512) void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
@@ -144,6 +144,7 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
                 load_params<VP>(P[v], gt[v], a.vparams, ld, i);
                 derive_cmd(C[v], (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i],
                            a.target[3 * ld + i]);
+                if constexpr (TRK) derive_traj(C[v], a.traj, ld, i);
             }
         }
 
@@ -177,8 +178,8 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
                     }
                 }
                 int ns;
-                if (out_step) ns = step<NR, true, true>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
-                else ns = step<NR, false, false>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
+                if (out_step) ns = step<NR, true, true, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
+                else ns = step<NR, false, false, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
                 if constexpr (OBS) {
                     c_sat += ns;
                     sat_last[v] = ns;
@@ -380,30 +381,36 @@ __global__ __launch_bounds__(kResetBlock) void k_reset_scatter(ScatterArgs a) {
 }
 
 // ---- kernel lookup ---------------------------------------------------------
-template <int NR, bool VP, bool RESET, bool OBS>
-static const void* pick_obs(int vpl, bool one) {
-    if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, true, OBS>);
-    if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 2, false, OBS>);
-    return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, false, OBS>);
+// Kernels with trajectories (mode 4) exist for one vehicle per lane and for
+// the quad and mixed rotor classes only.
+template <int NR, bool VP, bool RESET, bool OBS, bool TRK>
+static const void* pick_shape(int vpl, bool one) {
+    if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, true, OBS, TRK>);
+    if constexpr (!TRK) {
+        if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 2, false, OBS, TRK>);
+    }
+    return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, false, OBS, TRK>);
 }
 
-template <int NR, bool VP, bool RESET>
-static const void* pick_step(int vpl, bool one, bool obs) {
-    return obs ? pick_obs<NR, VP, RESET, true>(vpl, one) : pick_obs<NR, VP, RESET, false>(vpl, one);
+template <int NR, bool VP, bool RESET, bool TRK>
+static const void* pick_obs(int vpl, bool one, bool obs) {
+    return obs ? pick_shape<NR, VP, RESET, true, TRK>(vpl, one) : pick_shape<NR, VP, RESET, false, TRK>(vpl, one);
 }
 
-template <int NR>
+template <int NR, bool TRK>
 static const void* pick_nr(bool vp, bool reset, int vpl, bool one, bool obs) {
-    if (vp) return reset ? pick_step<NR, true, true>(vpl, one, obs) : pick_step<NR, true, false>(vpl, one, obs);
-    return reset ? pick_step<NR, false, true>(vpl, one, obs) : pick_step<NR, false, false>(vpl, one, obs);
+    if (vp) return reset ? pick_obs<NR, true, true, TRK>(vpl, one, obs) : pick_obs<NR, true, false, TRK>(vpl, one, obs);
+    return reset ? pick_obs<NR, false, true, TRK>(vpl, one, obs) : pick_obs<NR, false, false, TRK>(vpl, one, obs);
 }
 
-const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs) {
+const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs, bool trk) {
+    if (trk) return nr_class == 4 ? pick_nr<4, true>(vp, reset, vpl, one_step, obs)
+                                  : pick_nr<0, true>(vp, reset, vpl, one_step, obs);
     switch (nr_class) {
-        case 4: return pick_nr<4>(vp, reset, vpl, one_step, obs);
-        case 6: return pick_nr<6>(vp, reset, vpl, one_step, obs);
-        case 8: return pick_nr<8>(vp, reset, vpl, one_step, obs);
-        default: return pick_nr<0>(vp, reset, vpl, one_step, obs);
+        case 4: return pick_nr<4, false>(vp, reset, vpl, one_step, obs);
+        case 6: return pick_nr<6, false>(vp, reset, vpl, one_step, obs);
+        case 8: return pick_nr<8, false>(vp, reset, vpl, one_step, obs);
+        default: return pick_nr<0, false>(vp, reset, vpl, one_step, obs);
     }
 }
 

@@ -63,6 +63,9 @@ struct Cmd {
     int mode;
     float t0, t1, t2, t3;
     float ca, sa, cb, sb;
+    // trajectory rows of the tracking mode (kernels with trajectories only)
+    float xd0, xd1, xd2, vd0, vd1, vd2, ad0, ad1, ad2, cpd, spd;
+    float wd0, wd1, wd2, dwd0, dwd1, dwd2;
 };
 
 struct Wrench {
@@ -145,6 +148,16 @@ AG_DEV void derive_cmd(Cmd& C, int mode, float t0, float t1, float t2, float t3)
     sincosf(b, &C.sb, &C.cb);
 }
 
+// Trajectory rows of vehicle i (x_d, v_d, a_d, psi_d, Omega_d, dOmega_d).
+AG_DEV void derive_traj(Cmd& C, const float* __restrict__ tr, int64_t ld, int64_t i) {
+    C.xd0 = tr[i]; C.xd1 = tr[ld + i]; C.xd2 = tr[2 * ld + i];
+    C.vd0 = tr[3 * ld + i]; C.vd1 = tr[4 * ld + i]; C.vd2 = tr[5 * ld + i];
+    C.ad0 = tr[6 * ld + i]; C.ad1 = tr[7 * ld + i]; C.ad2 = tr[8 * ld + i];
+    sincosf(tr[9 * ld + i], &C.spd, &C.cpd);
+    C.wd0 = tr[10 * ld + i]; C.wd1 = tr[11 * ld + i]; C.wd2 = tr[12 * ld + i];
+    C.dwd0 = tr[13 * ld + i]; C.dwd1 = tr[14 * ld + i]; C.dwd2 = tr[15 * ld + i];
+}
+
 // Reverse-mode state of one vehicle for the tracking loss
 // sum_t |x_t - goal|^2 + w_omega |Omega_t|^2 over post-step states.
 struct Adj {
@@ -163,7 +176,7 @@ struct Adj {
 // which is then pulled back through integration, allocation (clamp
 // subgradient 1 inside [u_min, u_max], bounds included), the moment law,
 // the tilt extraction, the yaw readout and R(q).
-template <int NRC, bool WANT_W, bool WANT_U, bool GRAD>
+template <int NRC, bool WANT_W, bool WANT_U, bool GRAD, bool TRK = false>
 AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
                      float dt, float g, Wrench* W, float* u_out, Adj* adj) {
     constexpr int NR = RotorClass<NRC>::NR;
@@ -240,26 +253,86 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float E20 = T02 * P00 - sph * P10 + T22 * P20;
     const float E10 = T01 * P00 + cph * P10 + T21 * P20;
     const float E01 = cth * P01 - sth * P21;
-    const float eR0 = 0.5f * (E21 - E12);
-    const float eR1 = 0.5f * (E02 - E20);
-    const float eR2 = 0.5f * (E10 - E01);
+    float eR0 = 0.5f * (E21 - E12);
+    float eR1 = 0.5f * (E02 - E20);
+    float eR2 = 0.5f * (E10 - E01);
 
     // ---- e_Omega = Omega - psidot_d R^T e3 ---------------------------------
     const float psidot = m1 ? C.t3 : (m2 ? C.t2 : 0.0f);
     const float w0 = s[10], w1 = s[11], w2 = s[12];
-    const float eW0 = w0 - psidot * R20;
-    const float eW1 = w1 - psidot * R21;
-    const float eW2 = w2 - psidot * R22;
+    float eW0 = w0 - psidot * R20;
+    float eW1 = w1 - psidot * R21;
+    float eW2 = w2 - psidot * R22;
 
-    // ---- M = -kR e_R - kW e_Omega + Omega x J Omega, eq. (5) ---------------
+    // ---- gyroscopic term Omega x J Omega ------------------------------------
     const float JW0 = P.J0 * w0, JW1 = P.J1 * w1, JW2 = P.J2 * w2;
     const float gy0 = w1 * JW2 - w2 * JW1;
     const float gy1 = w2 * JW0 - w0 * JW2;
     const float gy2 = w0 * JW1 - w1 * JW0;
+
+    // ---- mode 4: full geometric tracking law (kernels with trajectories) ----
+    float ff0 = 0.0f, ff1 = 0.0f, ff2 = 0.0f;
+    bool m4 = false;
+    if constexpr (TRK) {
+        m4 = mode == 4;
+        // F = m (-kx e_x - kv e_v + a_d + g e3) in the inertial frame
+        const float F4x = P.m * (-P.kx_xy * (s[0] - C.xd0) - P.kv_xy * (vx - C.vd0) + C.ad0);
+        const float F4y = P.m * (-P.kx_xy * (s[1] - C.xd1) - P.kv_xy * (vy - C.vd1) + C.ad1);
+        const float F4z = P.m * (-P.kx_z * (s[2] - C.xd2) - P.kv_z * (vz - C.vd2) + C.ad2 + g);
+        const float f4 = F4x * R02 + F4y * R12 + F4z * R22;
+        // desired frame: b3 = F/|F|, b2 = b3 x b1d / |.|, b1 = b2 x b3
+        const float n4 = rsq(F4x * F4x + F4y * F4y + F4z * F4z);
+        const float b3x = F4x * n4, b3y = F4y * n4, b3z = F4z * n4;
+        float cx = -b3z * C.spd, cy = b3z * C.cpd, cz = b3x * C.spd - b3y * C.cpd;
+        float nc2 = cx * cx + cy * cy + cz * cz;
+        if (!(nc2 > 0.0f)) {          // heading parallel to b3: use e1, then e2
+            cx = 0.0f; cy = b3z; cz = -b3y;
+            nc2 = cy * cy + cz * cz;
+            if (!(nc2 > 0.0f)) { cx = -b3z; cy = 0.0f; cz = b3x; nc2 = cx * cx + cz * cz; }
+        }
+        const float ic = rsq(nc2);
+        const float b2x = cx * ic, b2y = cy * ic, b2z = cz * ic;
+        const float b1x = b2y * b3z - b2z * b3y, b1y = b2z * b3x - b2x * b3z, b1z = b2x * b3y - b2y * b3x;
+        // E = R_d^T R: E_ij = b_i . (column j of R)
+        const float G21 = b3x * R01 + b3y * R11 + b3z * R21, G12 = b2x * R02 + b2y * R12 + b2z * R22;
+        const float G02 = b1x * R02 + b1y * R12 + b1z * R22, G20 = b3x * R00 + b3y * R10 + b3z * R20;
+        const float G10 = b2x * R00 + b2y * R10 + b2z * R20, G01 = b1x * R01 + b1y * R11 + b1z * R21;
+        // R^T R_d Omega_d and R^T R_d dOmega_d
+        const float ax = b1x * C.wd0 + b2x * C.wd1 + b3x * C.wd2;
+        const float ay = b1y * C.wd0 + b2y * C.wd1 + b3y * C.wd2;
+        const float az = b1z * C.wd0 + b2z * C.wd1 + b3z * C.wd2;
+        const float c0 = R00 * ax + R10 * ay + R20 * az;
+        const float c1 = R01 * ax + R11 * ay + R21 * az;
+        const float c2 = R02 * ax + R12 * ay + R22 * az;
+        const float dx = b1x * C.dwd0 + b2x * C.dwd1 + b3x * C.dwd2;
+        const float dy = b1y * C.dwd0 + b2y * C.dwd1 + b3y * C.dwd2;
+        const float dz = b1z * C.dwd0 + b2z * C.dwd1 + b3z * C.dwd2;
+        const float d0 = R00 * dx + R10 * dy + R20 * dz;
+        const float d1 = R01 * dx + R11 * dy + R21 * dz;
+        const float d2 = R02 * dx + R12 * dy + R22 * dz;
+        f = m4 ? f4 : f;
+        eR0 = m4 ? 0.5f * (G21 - G12) : eR0;
+        eR1 = m4 ? 0.5f * (G02 - G20) : eR1;
+        eR2 = m4 ? 0.5f * (G10 - G01) : eR2;
+        eW0 = m4 ? w0 - c0 : eW0;
+        eW1 = m4 ? w1 - c1 : eW1;
+        eW2 = m4 ? w2 - c2 : eW2;
+        // feed-forward J (Omega x R^T R_d Omega_d - R^T R_d dOmega_d)
+        ff0 = m4 ? P.J0 * ((w1 * c2 - w2 * c1) - d0) : 0.0f;
+        ff1 = m4 ? P.J1 * ((w2 * c0 - w0 * c2) - d1) : 0.0f;
+        ff2 = m4 ? P.J2 * ((w0 * c1 - w1 * c0) - d2) : 0.0f;
+    }
+
+    // ---- M = -kR e_R - kW e_Omega + Omega x J Omega, eq. (5) ---------------
     float M0 = -P.kR0 * eR0 - P.kW0 * eW0 + gy0;
     float M1 = -P.kR1 * eR1 - P.kW1 * eW1 + gy1;
     float M2 = -P.kR2 * eR2 - P.kW2 * eW2 + gy2;
-    const bool known = m0 || m1 || m2 || m3;
+    if constexpr (TRK) {
+        M0 -= ff0;
+        M1 -= ff1;
+        M2 -= ff2;
+    }
+    const bool known = m0 || m1 || m2 || m3 || m4;
     M0 = m3 ? C.t1 : (known ? M0 : 0.0f);
     M1 = m3 ? C.t2 : (known ? M1 : 0.0f);
     M2 = m3 ? C.t3 : (known ? M2 : 0.0f);
@@ -496,10 +569,10 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     return nsat;
 }
 
-template <int NRC, bool WANT_W, bool WANT_U>
+template <int NRC, bool WANT_W, bool WANT_U, bool TRK = false>
 AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
                 float dt, float g, Wrench* W, float* u_out) {
-    return step_core<NRC, WANT_W, WANT_U, false>(s, C, P, gt, dt, g, W, u_out, nullptr);
+    return step_core<NRC, WANT_W, WANT_U, false, TRK>(s, C, P, gt, dt, g, W, u_out, nullptr);
 }
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------

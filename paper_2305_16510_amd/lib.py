@@ -4,7 +4,7 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libag.so")
 
-STATE_DIM, TARGET_DIM, VPARAM_DIM, NGAINS, WRENCH_DIM = 13, 4, 16, 10, 8
+STATE_DIM, TARGET_DIM, VPARAM_DIM, NGAINS, WRENCH_DIM, TRAJ_DIM = 13, 4, 16, 10, 8, 16
 AG_OK, AG_E_INVALID, AG_E_HIP, AG_E_NOMEM, AG_E_STATE, AG_E_UNSUPPORTED = range(6)
 FLAG_NONFINITE, FLAG_SATURATED, FLAG_RESET = 1, 2, 4
 
@@ -30,7 +30,7 @@ class Config(C.Structure):
                 ("vparams", C.c_void_p), ("wrench_out", C.c_void_p), ("rotor_out", C.c_void_p),
                 ("flags_out", C.c_void_p), ("reset_prob", C.c_float), ("auto_reset", C.c_int32),
                 ("reset_lo", C.c_float * 3), ("reset_hi", C.c_float * 3),
-                ("collect_stats", C.c_int32), ("autotune_scratch", C.c_int32)]
+                ("collect_stats", C.c_int32), ("autotune_scratch", C.c_int32), ("traj", C.c_void_p)]
 
 
 class Exec(C.Structure):

@@ -42,13 +42,14 @@ class Sim:
     """Owns device buffers for n vehicles and one library handle.
 
     Arrays are structure-of-arrays with leading dimension n: state [13, n],
-    target [4, n], mode [n] (int8), vparams [16, n] or None.
+    target [4, n], mode [n] (int8), vparams [16, n] or None, traj [16, n]
+    (tracking-mode trajectory rows) or None.
     """
 
     def __init__(self, groups, state0, mode, target, vparams=None, *, dt=0.01, g=9.81, seed=0,
                  index_base=0, reset_prob=0.0, auto_reset=False, reset_lo=(-5.0, -5.0, -5.0),
                  reset_hi=(5.0, 5.0, 5.0), collect_stats=False, outputs=False,
-                 autotune_scratch=False, device="cuda:0"):
+                 autotune_scratch=False, traj=None, device="cuda:0"):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required (no CPU fallback)")
@@ -63,6 +64,9 @@ class Sim:
             raise ValueError("state [13,n], target [4,n], mode [n] expected")
         if self.vparams is not None and self.vparams.shape != (L.VPARAM_DIM, self.n):
             raise ValueError("vparams [16,n] expected")
+        self.traj = None if traj is None else _dev(traj, F32, self.device)
+        if self.traj is not None and self.traj.shape != (L.TRAJ_DIM, self.n):
+            raise ValueError("traj [16,n] expected")
         self.wrench = self.rotors = self.flags = None
         if outputs:
             self.wrench = torch.zeros(L.WRENCH_DIM, self.n, dtype=F32, device=self.device)
@@ -85,6 +89,7 @@ class Sim:
             cfg.reset_lo[j], cfg.reset_hi[j] = reset_lo[j], reset_hi[j]
         cfg.collect_stats = int(bool(collect_stats))
         cfg.autotune_scratch = int(bool(autotune_scratch))
+        cfg.traj = _ptr(self.traj)
         self._cfg = cfg
         nbytes = C.c_size_t(0)
         L.check(self._lib.ag_workspace_size(C.byref(cfg), C.byref(nbytes)), None, "ag_workspace_size")
