@@ -193,6 +193,24 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen);
 ag_status ag_reset(ag_handle h, const uint8_t* mask_in, int64_t step, uint8_t* mask_out,
                    int32_t* indices_out, int32_t* count_out);
 
+/* Obstacle poses at environment reset (Sec. V, asset manager): every
+ * environment (one per vehicle, index i) holds n_obs obstacle slots.  For each
+ * environment in env_mask (device uint8[n], nonzero = reset; NULL = all), slot
+ * k gets a position lo + (hi - lo) * frac with frac_a in [frac_lo_a, frac_hi_a]
+ * of the environment box (env_lo/env_hi device [3][ld] per environment, or
+ * NULL to use box_lo/box_hi for all) and an attitude from Z-Y-X Euler angles
+ * (roll, pitch, yaw) in [eul_lo, eul_hi]; dimensions whose lock bit is set
+ * take lock_val (a fraction for x, y, z, an angle for roll, pitch, yaw).
+ * slots: device [n_obs][20] floats = frac_lo(3), frac_hi(3), eul_lo(3),
+ * eul_hi(3), lock bits (x, y, z, roll, pitch, yaw as bits 0-5, stored as a
+ * float), lock_val(6), unused(1).  Output obstacle i*n_obs + k as rows
+ * (x, y, z, qw, qx, qy, qz) of out (device [7][out_ld], out_ld >= n*n_obs);
+ * rows of environments not reset are left untouched.  Draws come from the
+ * handle's counter-based generator at step `step` (0 <= step < 2^32). */
+ag_status ag_randomize_obstacles(ag_handle h, int32_t n_obs, const float* slots, const float* env_lo,
+                                 const float* env_hi, const float* box_lo, const float* box_hi,
+                                 const uint8_t* env_mask, int64_t step, float* out, int64_t out_ld);
+
 /* Synchronise and read the statistics (clear = 1 zeroes the counters). */
 ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear);
 

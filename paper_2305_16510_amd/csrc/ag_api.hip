@@ -720,6 +720,37 @@ ag_status ag_reset(ag_handle h, const uint8_t* mask_in, int64_t step, uint8_t* m
     return launch(h, reset_scatter_kernel(), dim3(nb), dim3(kResetBlock), 0, &ca);
 }
 
+ag_status ag_randomize_obstacles(ag_handle h, int32_t n_obs, const float* slots, const float* env_lo,
+                                 const float* env_hi, const float* box_lo, const float* box_hi,
+                                 const uint8_t* env_mask, int64_t step, float* out, int64_t out_ld) {
+    AG_CHECK_HANDLE(h);
+    if (n_obs < 1 || !slots || !out) return set_err(h, AG_E_INVALID, "n_obs >= 1, slots and out are required");
+    if (step < 0 || step > 4294967295LL) return set_err(h, AG_E_INVALID, "step must be in [0, 2^32)");
+    const long long total = h->cfg.n * (long long)n_obs;
+    if (out_ld < total) return set_err(h, AG_E_INVALID, "out_ld must be >= n * n_obs");
+    if ((env_lo == nullptr) != (env_hi == nullptr)) return set_err(h, AG_E_INVALID, "env_lo and env_hi go together");
+    if (!env_lo && (!box_lo || !box_hi)) return set_err(h, AG_E_INVALID, "box_lo and box_hi needed without env boxes");
+    ObstArgs a{};
+    a.slots = slots;
+    a.env_lo = env_lo;
+    a.env_hi = env_hi;
+    a.mask = env_mask;
+    a.out = out;
+    a.n_env = h->cfg.n;
+    a.ld = h->cfg.ld;
+    a.out_ld = out_ld;
+    a.t = step;
+    a.n_obs = n_obs;
+    a.key0 = h->key0;
+    a.key1 = h->key1;
+    a.index_base = (uint32_t)h->cfg.index_base;
+    for (int d = 0; d < 3; ++d) {
+        a.box_lo[d] = box_lo ? box_lo[d] : 0.0f;
+        a.box_hi[d] = box_hi ? box_hi[d] : 0.0f;
+    }
+    return launch(h, obstacles_kernel(), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, &a);
+}
+
 ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear) {
     AG_CHECK_HANDLE(h);
     if (!out) return AG_E_INVALID;

@@ -145,4 +145,18 @@ struct ClearArgs {
 
 constexpr int kResetBlock = 256;
 
+struct ObstArgs {
+    const float* slots;        // [n_obs][20]
+    const float* env_lo;       // [3][ld] or null (box_lo for every env)
+    const float* env_hi;
+    const uint8_t* mask;       // [n_env] or null (all)
+    float* out;                // [7][out_ld]
+    long long n_env, ld, out_ld, t;
+    int32_t n_obs;
+    uint32_t key0, key1, index_base;
+    float box_lo[3], box_hi[3];
+};
+
+const void* obstacles_kernel();
+
 }  // namespace ag

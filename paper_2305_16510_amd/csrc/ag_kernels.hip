@@ -380,6 +380,51 @@ __global__ __launch_bounds__(kResetBlock) void k_reset_scatter(ScatterArgs a) {
     if (m) a.indices[a.offsets[blockIdx.x] + before + rank_in_wave] = (int32_t)i;
 }
 
+// ---- obstacle poses at environment reset -----------------------------------
+// One lane per (environment, obstacle slot).  Position: fraction of the env
+// box per axis drawn in [frac_lo, frac_hi]; attitude: Z-Y-X Euler angles in
+// [eul_lo, eul_hi]; locked dimensions take the slot's constant.  Uniforms from
+// Philox(counter = (env, lo32(t), slot, "OB" | j)), j = 0, 1.
+constexpr uint32_t TAG_OBST = 0x4F420000u;
+
+__global__ __launch_bounds__(256) void k_obstacles(ObstArgs a) {
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.n_env * a.n_obs) return;
+    const long long e = idx / a.n_obs;
+    const int k = (int)(idx - e * a.n_obs);
+    if (a.mask && a.mask[e] == 0) return;
+    const float* row = a.slots + (long long)k * 20;
+    const uint32_t ge = a.index_base + (uint32_t)e;
+    const uint4 w0 = philox(make_uint4(ge, (uint32_t)a.t, (uint32_t)k, TAG_OBST | 0u), a.key0, a.key1);
+    const uint4 w1 = philox(make_uint4(ge, (uint32_t)a.t, (uint32_t)k, TAG_OBST | 1u), a.key0, a.key1);
+    const float u[6] = {u24(w0.x), u24(w0.y), u24(w0.z), u24(w0.w), u24(w1.x), u24(w1.y)};
+    const int bits = (int)row[12];
+    float pos[3], ang[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const float lo = a.env_lo ? a.env_lo[d * a.ld + e] : a.box_lo[d];
+        const float hi = a.env_hi ? a.env_hi[d * a.ld + e] : a.box_hi[d];
+        float fr = row[d] + (row[3 + d] - row[d]) * u[d];
+        fr = (bits >> d & 1) ? row[13 + d] : fr;
+        pos[d] = lo + (hi - lo) * fr;
+        const float an = row[6 + d] + (row[9 + d] - row[6 + d]) * u[3 + d];
+        ang[d] = (bits >> (3 + d) & 1) ? row[16 + d] : an;
+    }
+    float sr, cr, sp, cp, sy, cy;
+    sincosf(0.5f * ang[0], &sr, &cr);
+    sincosf(0.5f * ang[1], &sp, &cp);
+    sincosf(0.5f * ang[2], &sy, &cy);
+    // qz(yaw) (x) qy(pitch) (x) qx(roll)
+    const float q[4] = {cy * cp * cr + sy * sp * sr, cy * cp * sr - sy * sp * cr,
+                        cy * sp * cr + sy * cp * sr, sy * cp * cr - cy * sp * sr};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) a.out[d * a.out_ld + idx] = pos[d];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) a.out[(3 + d) * a.out_ld + idx] = q[d];
+}
+
+const void* obstacles_kernel() { return reinterpret_cast<const void*>(&k_obstacles); }
+
 // ---- kernel lookup ---------------------------------------------------------
 // Kernels with trajectories (mode 4) exist for one vehicle per lane and for
 // the quad and mixed rotor classes only.

@@ -10,7 +10,7 @@ FLAG_NONFINITE, FLAG_SATURATED, FLAG_RESET = 1, 2, 4
 
 EXPORTS = [
     "ag_workspace_size", "ag_create", "ag_destroy", "ag_set_targets", "ag_step", "ag_prepare", "ag_set_exec",
-    "ag_get_exec", "ag_autotune", "ag_reset", "ag_get_stats", "ag_get_step", "ag_set_step",
+    "ag_get_exec", "ag_autotune", "ag_reset", "ag_randomize_obstacles", "ag_get_stats", "ag_get_step", "ag_set_step",
     "ag_rollout_workspace_size", "ag_rollout_forward", "ag_rollout_adjoint", "ag_sync",
     "ag_last_error", "ag_status_string",
 ]
@@ -75,6 +75,8 @@ def load():
         "ag_get_exec": ([H, C.POINTER(Exec)], C.c_int),
         "ag_autotune": ([H, C.c_int32, C.POINTER(Exec)], C.c_int),
         "ag_reset": ([H, P, C.c_int64, P, P, P], C.c_int),
+        "ag_randomize_obstacles": ([H, C.c_int32, P, P, P, C.POINTER(C.c_float), C.POINTER(C.c_float), P,
+                                    C.c_int64, P, C.c_int64], C.c_int),
         "ag_get_stats": ([H, C.POINTER(Stats), C.c_int32], C.c_int),
         "ag_get_step": ([H, C.POINTER(C.c_int64)], C.c_int),
         "ag_set_step": ([H, C.c_int64], C.c_int),

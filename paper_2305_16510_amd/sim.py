@@ -183,6 +183,20 @@ class Sim:
         self.sync()
         return m_out, idx[: int(cnt.item())]
 
+    def randomize_obstacles(self, slots, out, step, mask=None, env_lo=None, env_hi=None, box_lo=None,
+                            box_hi=None):
+        """Redraw obstacle poses (rows x, y, z, qw, qx, qy, qz of ``out`` [7, >= n*n_obs])
+        of the environments in ``mask`` (all when None); slots [n_obs, 20]."""
+        sl = _dev(slots, F32, self.device)
+        m = None if mask is None else _dev(mask, torch.uint8, self.device)
+        lo = None if env_lo is None else _dev(env_lo, F32, self.device)
+        hi = None if env_hi is None else _dev(env_hi, F32, self.device)
+        blo = None if box_lo is None else (C.c_float * 3)(*box_lo)
+        bhi = None if box_hi is None else (C.c_float * 3)(*box_hi)
+        self._call("ag_randomize_obstacles", C.c_int32(int(sl.shape[0])), _ptr(sl), _ptr(lo), _ptr(hi), blo, bhi,
+                   _ptr(m), C.c_int64(int(step)), _ptr(out), C.c_int64(int(out.shape[1])))
+        self._keep = (sl, m, lo, hi)
+
     def stats(self, clear=False):
         s = L.Stats()
         self._call("ag_get_stats", C.byref(s), C.c_int32(int(bool(clear))))
