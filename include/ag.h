@@ -211,6 +211,32 @@ ag_status ag_randomize_obstacles(ag_handle h, int32_t n_obs, const float* slots,
                                  const float* env_hi, const float* box_lo, const float* box_hi,
                                  const uint8_t* env_mask, int64_t step, float* out, int64_t out_ld);
 
+/* Pinhole depth camera mounted on each vehicle (Sec. III: cameras with a
+ * configurable pose on the robot; Sec. I and VII: ray casting for depth).
+ * Camera frame: x forward, y left, z up; pixel (u, v) of a width x height
+ * image looks along normalize(1, -(u + 1/2 - W/2)/f, -(v + 1/2 - H/2)/f) with
+ * f = (W/2) / tan(hfov/2). */
+typedef struct {
+    int32_t width, height;
+    float hfov;             /* horizontal field of view [rad], in (0, pi) */
+    float max_depth;        /* [m]: value of pixels with no hit or a deeper hit */
+    float floor_z;          /* floor plane z [m] seen from above; NaN = no floor */
+    float mount_pos[3];     /* camera position in the body frame [m] */
+    float mount_quat[4];    /* camera attitude in the body frame (w, x, y, z), unit */
+} ag_camera;
+
+/* Depth images of vehicles [first, first + count): depth[(i - first)][v][u]
+ * (device, count * height * width floats) is the distance along the optical
+ * axis to the first entry of the ray into an obstacle of vehicle i's
+ * environment or into the floor (the exit when the camera is inside an
+ * obstacle), or max_depth.  Obstacles: n_obs (<= 256) per environment with
+ * poses in rows (x, y, z, qw, qx, qy, qz) of obst (device [7][obst_ld],
+ * obstacle i*n_obs + k, the layout of ag_randomize_obstacles) and shapes
+ * (device [n_obs][8]): type 0 box (half extents x, y, z), 1 sphere (radius),
+ * 2 cylinder along its z axis (radius, half height). */
+ag_status ag_render_depth(ag_handle h, const ag_camera* cam, int32_t n_obs, const float* shapes, const float* obst,
+                          int64_t obst_ld, int64_t first, int64_t count, float* depth);
+
 /* Synchronise and read the statistics (clear = 1 zeroes the counters). */
 ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear);
 

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libag.so")
 PROBE_LIB = os.path.join(LIBDIR, "libagprobe.so")
-SOURCES = ["ag_kernels.hip", "ag_rollout.hip", "ag_api.hip"]
+SOURCES = ["ag_kernels.hip", "ag_rollout.hip", "ag_camera.hip", "ag_api.hip"]
 PROBE_SOURCES = ["ag_probe.hip"]
 ARCH = os.environ.get("AG_OFFLOAD_ARCH", "gfx950")
 

@@ -751,6 +751,46 @@ ag_status ag_randomize_obstacles(ag_handle h, int32_t n_obs, const float* slots,
     return launch(h, obstacles_kernel(), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, &a);
 }
 
+ag_status ag_render_depth(ag_handle h, const ag_camera* cam, int32_t n_obs, const float* shapes, const float* obst,
+                          int64_t obst_ld, int64_t first, int64_t count, float* depth) {
+    AG_CHECK_HANDLE(h);
+    if (!cam || !depth) return set_err(h, AG_E_INVALID, "camera and depth are required");
+    if (cam->width < 1 || cam->height < 1 || !(cam->hfov > 0.0f && cam->hfov < 3.14159f) ||
+        !(cam->max_depth > 0.0f))
+        return set_err(h, AG_E_INVALID, "camera needs width, height >= 1, 0 < hfov < pi, max_depth > 0");
+    if (n_obs < 0 || n_obs > 256 || (n_obs > 0 && (!shapes || !obst)))
+        return set_err(h, AG_E_INVALID, "0 <= n_obs <= 256 with shapes and obst");
+    if (first < 0 || count < 0 || first + count > h->cfg.n) return set_err(h, AG_E_INVALID, "vehicle range out of bounds");
+    if (n_obs > 0 && obst_ld < h->cfg.n * (long long)n_obs) return set_err(h, AG_E_INVALID, "obst_ld must be >= n * n_obs");
+    if (count == 0) return AG_OK;
+    CameraArgs a{};
+    a.state = h->cfg.state;
+    a.shapes = shapes;
+    a.obst = obst;
+    a.depth = depth;
+    a.ld = h->cfg.ld;
+    a.obst_ld = obst_ld;
+    a.n_obs = n_obs;
+    a.W = cam->width;
+    a.H = cam->height;
+    a.has_floor = std::isnan(cam->floor_z) ? 0 : 1;
+    a.floor_z = cam->floor_z;
+    a.inv_f = (float)(std::tan(0.5 * (double)cam->hfov) / (0.5 * (double)cam->width));
+    a.max_depth = cam->max_depth;
+    for (int k = 0; k < 3; ++k) a.mount_p[k] = cam->mount_pos[k];
+    for (int k = 0; k < 4; ++k) a.mount_q[k] = cam->mount_quat[k];
+    const unsigned tiles = (unsigned)(((cam->width + 63) / 64) * ((cam->height + 3) / 4));
+    const long long chunk = 65535;
+    for (long long f0 = 0; f0 < count; f0 += chunk) {
+        a.first = first + f0;
+        a.depth = depth + f0 * (long long)cam->width * cam->height;
+        const unsigned cnt = (unsigned)std::min(chunk, count - f0);
+        ag_status st = launch(h, depth_kernel(), dim3(tiles, cnt), dim3(256), 0, &a);
+        if (st != AG_OK) return st;
+    }
+    return AG_OK;
+}
+
 ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear) {
     AG_CHECK_HANDLE(h);
     if (!out) return AG_E_INVALID;

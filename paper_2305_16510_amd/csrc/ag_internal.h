@@ -159,4 +159,17 @@ struct ObstArgs {
 
 const void* obstacles_kernel();
 
+struct CameraArgs {
+    const float* state;        // [13][ld] vehicle poses
+    const float* shapes;       // [n_obs][8]
+    const float* obst;         // [7][obst_ld]
+    float* depth;              // [count][H][W]
+    long long ld, obst_ld, first;
+    int32_t n_obs, W, H, has_floor;
+    float inv_f, max_depth, floor_z;
+    float mount_p[3], mount_q[4];
+};
+
+const void* depth_kernel();
+
 }  // namespace ag

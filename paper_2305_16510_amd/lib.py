@@ -10,7 +10,7 @@ FLAG_NONFINITE, FLAG_SATURATED, FLAG_RESET = 1, 2, 4
 
 EXPORTS = [
     "ag_workspace_size", "ag_create", "ag_destroy", "ag_set_targets", "ag_step", "ag_prepare", "ag_set_exec",
-    "ag_get_exec", "ag_autotune", "ag_reset", "ag_randomize_obstacles", "ag_get_stats", "ag_get_step", "ag_set_step",
+    "ag_get_exec", "ag_autotune", "ag_reset", "ag_randomize_obstacles", "ag_render_depth", "ag_get_stats", "ag_get_step", "ag_set_step",
     "ag_rollout_workspace_size", "ag_rollout_forward", "ag_rollout_adjoint", "ag_sync",
     "ag_last_error", "ag_status_string",
 ]
@@ -77,6 +77,7 @@ def load():
         "ag_reset": ([H, P, C.c_int64, P, P, P], C.c_int),
         "ag_randomize_obstacles": ([H, C.c_int32, P, P, P, C.POINTER(C.c_float), C.POINTER(C.c_float), P,
                                     C.c_int64, P, C.c_int64], C.c_int),
+        "ag_render_depth": ([H, C.POINTER(Camera), C.c_int32, P, P, C.c_int64, C.c_int64, C.c_int64, P], C.c_int),
         "ag_get_stats": ([H, C.POINTER(Stats), C.c_int32], C.c_int),
         "ag_get_step": ([H, C.POINTER(C.c_int64)], C.c_int),
         "ag_set_step": ([H, C.c_int64], C.c_int),
@@ -107,3 +108,8 @@ def check(status, handle=None, what=""):
         L = load()
         detail = L.ag_last_error(handle).decode() if handle else L.ag_status_string(status).decode()
         raise AgError(status, f"{what}: {detail}")
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("hfov", C.c_float), ("max_depth", C.c_float),
+                ("floor_z", C.c_float), ("mount_pos", C.c_float * 3), ("mount_quat", C.c_float * 4)]

@@ -197,6 +197,22 @@ class Sim:
                    _ptr(m), C.c_int64(int(step)), _ptr(out), C.c_int64(int(out.shape[1])))
         self._keep = (sl, m, lo, hi)
 
+    def render_depth(self, shapes, obst, width, height, hfov, max_depth, floor_z=float("nan"),
+                     mount_pos=(0.0, 0.0, 0.0), mount_quat=(1.0, 0.0, 0.0, 0.0), first=0, count=None, out=None):
+        """Depth images [count, height, width] of vehicles [first, first+count)."""
+        count = self.n - first if count is None else count
+        cam = L.Camera(int(width), int(height), float(hfov), float(max_depth), float(floor_z),
+                       (C.c_float * 3)(*mount_pos), (C.c_float * 4)(*mount_quat))
+        sh = None if shapes is None else _dev(shapes, F32, self.device)
+        n_obs = 0 if sh is None else int(sh.shape[0])
+        if out is None:
+            out = torch.empty(count, height, width, dtype=F32, device=self.device)
+        self._call("ag_render_depth", C.byref(cam), C.c_int32(n_obs), _ptr(sh), _ptr(obst),
+                   C.c_int64(0 if obst is None else int(obst.shape[1])), C.c_int64(first), C.c_int64(count),
+                   _ptr(out))
+        self._keep = (sh,)
+        return out
+
     def stats(self, clear=False):
         s = L.Stats()
         self._call("ag_get_stats", C.byref(s), C.c_int32(int(bool(clear))))

@@ -1,0 +1,84 @@
+"""Depth ray casting on the GPU against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import workloads
+from oracle import obstacles, raycast
+from parity import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def scene(n, n_obs, seed):
+    rng = np.random.default_rng(seed)
+    shapes = np.zeros((n_obs, 8), np.float32)
+    shapes[:, 0] = np.arange(n_obs) % 3
+    shapes[:, 1] = rng.uniform(0.2, 0.8, n_obs)
+    shapes[:, 2] = rng.uniform(0.2, 0.8, n_obs)
+    shapes[:, 3] = rng.uniform(0.2, 0.8, n_obs)
+    slots = np.stack([obstacles.slot_row((0.55, 0.05, 0.1), (0.95, 0.95, 0.9), (-1, -1, -math.pi), (1, 1, math.pi))
+                      for _ in range(n_obs)])
+    return shapes, slots
+
+
+def compare(gpu, ref, maxd):
+    """Relative depth error on pixels away from silhouettes (all 4-neighbours
+    within 1% in the oracle's image); edge pixels are counted, not compared."""
+    g = gpu.astype(np.float64)
+    pad = np.pad(ref, ((0, 0), (1, 1), (1, 1)), mode="edge")
+    nb = np.stack([pad[:, :-2, 1:-1], pad[:, 2:, 1:-1], pad[:, 1:-1, :-2], pad[:, 1:-1, 2:]])
+    smooth = (np.abs(nb - ref[None]) <= 0.01 * ref[None]).all(0)
+    err = np.abs(g - ref) / np.maximum(ref, 1e-6)
+    return err[smooth].max(), 1.0 - smooth.mean(), (err[~smooth] > 1e-3).mean() if (~smooth).any() else 0.0
+
+
+def render_case(n, n_obs, W, H, seed, floor=0.0):
+    from paper_2305_16510_amd.sim import Sim
+    wl = workloads.c1_parity(n=n, seed=seed)
+    wl.state0[0:3] = np.array([[0.5], [5.0], [1.5]], np.float32) + wl.state0[0:3] * 0.2
+    sim = Sim.from_workload(wl)
+    shapes, slots = scene(n, n_obs, seed)
+    obst = torch.zeros(7, n * n_obs, device="cuda")
+    obst[3] = 1.0
+    sim.randomize_obstacles(slots, obst, step=1, box_lo=(0.0, 0.0, 0.0), box_hi=(10.0, 10.0, 3.0))
+    mount_q = Rotation.from_euler("y", 8, degrees=True).as_quat()[[3, 0, 1, 2]]
+    depth = sim.render_depth(shapes, obst, W, H, 1.5, 10.0, floor_z=floor, mount_pos=(0.1, 0.0, 0.05),
+                             mount_quat=tuple(mount_q))
+    sim.sync()
+    st = sim.state.cpu().numpy().T.astype(np.float64)
+    ob = obst.cpu().numpy().T.astype(np.float64).reshape(n, n_obs, 7)
+    d = depth.cpu().numpy()
+    sim.close()
+    return d, st, ob, shapes, mount_q
+
+
+def test_depth_images_match_oracle():
+    need_gpu()
+    n, n_obs, W, H = 12, 15, 96, 54
+    d, st, ob, shapes, mq = render_case(n, n_obs, W, H, 80)
+    ref = raycast.render(st[:, 0:3], st[:, 6:10], np.array([0.1, 0.0, 0.05]), mq, shapes.astype(np.float64),
+                         ob, 0.0, W, H, 1.5, 10.0)
+    emax, edge_frac, edge_bad = compare(d, ref, 10.0)
+    print("depth: max rel err off edges %.2e, edge pixels %.2f%%, edge mismatches %.2f%%" %
+          (emax, 100 * edge_frac, 100 * edge_bad))
+    assert emax <= 1e-4
+    assert edge_frac < 0.1
+    assert ((ref < 10.0).mean() > 0.2) and ((ref == 10.0).mean() > 0.01)
+
+
+def test_full_resolution_sampled_cameras():
+    """2^10 vehicles with 270 x 480 depth cameras (the paper's camera
+    benchmark shape); 4 sampled cameras checked against the oracle."""
+    need_gpu()
+    n, n_obs, W, H = 1024, 20, 480, 270
+    d, st, ob, shapes, mq = render_case(n, n_obs, W, H, 81)
+    idx = np.array([0, 333, 700, 1023])
+    ref = raycast.render(st[idx, 0:3], st[idx, 6:10], np.array([0.1, 0.0, 0.05]), mq, shapes.astype(np.float64),
+                         ob[idx], 0.0, W, H, 1.5, 10.0)
+    emax, edge_frac, _ = compare(d[idx], ref, 10.0)
+    print("full res: max rel err off edges %.2e, edge pixels %.2f%%" % (emax, 100 * edge_frac))
+    assert emax <= 1e-4 and edge_frac < 0.1
