@@ -160,6 +160,44 @@ def bench_large(sync):
                             "what": "forward + adjoint + one SGD step on the 10 gains"}}
 
 
+def bench_camera(sync, n=1024, n_obs=20, W=480, H=270, reps=5):
+    """Depth cameras: 2^10 vehicles with 270 x 480 images (the paper's camera
+    benchmark shape, Sec. VI) in environments with 20 primitive obstacles
+    placed by the reset randomisation."""
+    import math
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2305_16510_amd.sim import Sim
+    wl = workloads.c1_parity(n=n, seed=90)
+    wl.state0[0:3] = np.array([[0.5], [5.0], [1.5]], np.float32) + wl.state0[0:3] * 0.2
+    sim = Sim.from_workload(wl)
+    rng = np.random.default_rng(91)
+    shapes = np.zeros((n_obs, 8), np.float32)
+    shapes[:, 0] = np.arange(n_obs) % 3
+    shapes[:, 1:4] = rng.uniform(0.2, 0.8, (n_obs, 3))
+    slot = [0.55, 0.05, 0.1, 0.95, 0.95, 0.9, -1, -1, -math.pi, 1, 1, math.pi, 0, 0, 0, 0, 0, 0, 0, 0]
+    slots = np.array([slot] * n_obs, np.float32)
+    obst = torch.zeros(7, n * n_obs, device="cuda")
+    obst[3] = 1.0
+    sim.randomize_obstacles(slots, obst, step=1, box_lo=(0.0, 0.0, 0.0), box_hi=(10.0, 10.0, 3.0))
+    out = torch.empty(n, H, W, device="cuda")
+    sh = torch.as_tensor(shapes).cuda()
+    sim.render_depth(sh, obst, W, H, 1.5, 10.0, floor_z=0.0, out=out)
+    sync()
+    ts = [event_time(sim.stream, lambda: sim.render_depth(sh, obst, W, H, 1.5, 10.0, floor_z=0.0, out=out))
+          for _ in range(reps)]
+    t_obs = event_time(sim.stream, lambda: sim.randomize_obstacles(slots, obst, step=2, box_lo=(0.0, 0.0, 0.0),
+                                                                   box_hi=(10.0, 10.0, 3.0)))
+    sim.close()
+    t = min(ts)
+    log(f"depth cameras: {n} x {W}x{H}, {n_obs} obstacles: {t * 1e3:.2f} ms per frame set = {n / t:.3e} images/s")
+    return {"workload": f"{n} vehicles, {W}x{H} depth images, {n_obs} box/sphere/cylinder obstacles per env",
+            "seconds_per_frame_set": t, "images_per_s": n / t, "rays_per_s": n * W * H / t,
+            "obstacle_randomisation_s": t_obs,
+            "paper_context": {"images_per_s": 1800, "hardware": "RTX 3090, engine renderer (Sec. VI)"}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +337,7 @@ def main():
         out["adjoint"] = bench_adjoint(sync)
         out["uneven_groups"] = bench_uneven(sync)
         out["large_resets"] = bench_large(sync)
+        out["depth_cameras"] = bench_camera(sync)
 
     sim.close()
     del sim
