@@ -119,6 +119,8 @@ typedef struct {
     int32_t collect_stats;  /* 1: ag_step accumulates the ag_stats counters and final-state sums */
     int32_t autotune_scratch;  /* 1: workspace holds scratch state so ag_autotune leaves results untouched */
     const float* traj;      /* device [16][ld] or NULL: trajectory rows of mode 4 (see AG_MODE_TRACK) */
+    float* goal;            /* device [3][ld] or NULL: goal of the goal-reaching task (ag_observe);
+                               every reset (explicit or automatic) redraws it for the reset vehicles */
 } ag_config;
 
 /* Execution policy of ag_step.  kind 0: one launch of the per-step kernel per
@@ -236,6 +238,30 @@ typedef struct {
  * 2 cylinder along its z axis (radius, half height). */
 ag_status ag_render_depth(ag_handle h, const ag_camera* cam, int32_t n_obs, const float* shapes, const float* obst,
                           int64_t obst_ld, int64_t first, int64_t count, float* depth);
+
+/* Goal-reaching task of a Gym-style vectorised environment (Sec. III:
+ * Gym-style interfaces; Sec. I: goal reaching with attitude and velocity
+ * commands).  Actions (device [4][act_ld], one column per vehicle) are
+ * clamped to [-1, 1] and mapped to commands target = offset + scale * a
+ * (row-wise, 4 rows) for every vehicle, whose mode is set to `mode`.
+ * Observation, reward and termination after a step, per vehicle:
+ *   obs    = (goal - x, v, q, Omega)            rows of obs (device [13][obs_ld])
+ *   reward = -|goal - x| - w_v |v| - w_omega |Omega| + bonus if |goal - x| < r_goal
+ *   done   = episode >= max_steps or |goal - x| > r_far or a non-finite state
+ * with goal = cfg.goal (or target rows 0-2 when cfg.goal is NULL) and the
+ * per-vehicle episode counter (device int32[n]) incremented first and reset to
+ * 0 for finished vehicles.  Non-finite vehicles get a zero observation and
+ * reward.  With advance = 0 only obs is written (no counter, reward or done),
+ * e.g. after resetting the finished vehicles with ag_reset(done mask). */
+typedef struct {
+    float w_v, w_omega, bonus, r_goal, r_far;
+    int32_t max_steps;
+} ag_task;
+
+ag_status ag_apply_actions(ag_handle h, const float* actions, int64_t act_ld, int32_t mode, const float* scale,
+                           const float* offset);
+ag_status ag_observe(ag_handle h, const ag_task* task, int32_t advance, float* obs, int64_t obs_ld, float* reward,
+                     uint8_t* done, int32_t* episode);
 
 /* Synchronise and read the statistics (clear = 1 zeroes the counters). */
 ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear);

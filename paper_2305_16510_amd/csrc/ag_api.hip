@@ -245,6 +245,7 @@ StepArgs base_args(ag_handle h) {
     a.target = h->cfg.target;
     a.vparams = h->cfg.vparams;
     a.traj = h->cfg.traj;
+    a.goal = h->cfg.goal;
     a.gtab = h->gtab;
     a.goff = h->goff;
     a.wrench_out = h->cfg.wrench_out;
@@ -696,6 +697,7 @@ ag_status ag_reset(ag_handle h, const uint8_t* mask_in, int64_t step, uint8_t* m
     a.mode = h->cfg.mode;
     a.target = h->cfg.target;
     a.mask_in = mask_in;
+    a.goal = h->cfg.goal;
     const bool need_scan = indices_out || count_out;
     a.mask_out = mask_out ? mask_out : (need_scan ? h->mask_buf : nullptr);
     a.block_counts = need_scan ? h->block_counts : nullptr;
@@ -789,6 +791,55 @@ ag_status ag_render_depth(ag_handle h, const ag_camera* cam, int32_t n_obs, cons
         if (st != AG_OK) return st;
     }
     return AG_OK;
+}
+
+ag_status ag_apply_actions(ag_handle h, const float* actions, int64_t act_ld, int32_t mode, const float* scale,
+                           const float* offset) {
+    AG_CHECK_HANDLE(h);
+    if (!actions || !scale || !offset) return set_err(h, AG_E_INVALID, "actions, scale and offset are required");
+    if (act_ld < h->cfg.n) return set_err(h, AG_E_INVALID, "act_ld must be >= n");
+    if (mode < 0 || mode > 3) return set_err(h, AG_E_INVALID, "action mode must be 0..3");
+    ActArgs a{};
+    a.actions = actions;
+    a.target = h->cfg.target;
+    a.mode = h->cfg.mode;
+    a.n = h->cfg.n;
+    a.ld = h->cfg.ld;
+    a.act_ld = act_ld;
+    a.new_mode = mode;
+    for (int r = 0; r < 4; ++r) {
+        a.scale[r] = scale[r];
+        a.offset[r] = offset[r];
+    }
+    return launch(h, actions_kernel(), dim3((unsigned)((h->cfg.n + 255) / 256)), dim3(256), 0, &a);
+}
+
+ag_status ag_observe(ag_handle h, const ag_task* task, int32_t advance, float* obs, int64_t obs_ld, float* reward,
+                     uint8_t* done, int32_t* episode) {
+    AG_CHECK_HANDLE(h);
+    if (!task || !obs) return set_err(h, AG_E_INVALID, "task and obs are required");
+    if (obs_ld < h->cfg.n) return set_err(h, AG_E_INVALID, "obs_ld must be >= n");
+    if (advance && (!reward || !done || !episode))
+        return set_err(h, AG_E_INVALID, "reward, done and episode are required when advancing");
+    TaskArgs a{};
+    a.state = h->cfg.state;
+    a.goal = h->cfg.goal ? h->cfg.goal : h->cfg.target;
+    a.goal_ld = h->cfg.ld;
+    a.obs = obs;
+    a.reward = reward;
+    a.done = done;
+    a.episode = episode;
+    a.n = h->cfg.n;
+    a.ld = h->cfg.ld;
+    a.obs_ld = obs_ld;
+    a.advance = advance ? 1 : 0;
+    a.max_steps = task->max_steps;
+    a.w_v = task->w_v;
+    a.w_omega = task->w_omega;
+    a.bonus = task->bonus;
+    a.r_goal = task->r_goal;
+    a.r_far = task->r_far;
+    return launch(h, observe_kernel(), dim3((unsigned)((h->cfg.n + 255) / 256)), dim3(256), 0, &a);
 }
 
 ag_status ag_get_stats(ag_handle h, ag_stats* out, int32_t clear) {

@@ -37,6 +37,7 @@ struct StepArgs {
     float* wrench_out;         // [8][ld] or null
     float* rotor_out;          // [8][ld] or null
     uint8_t* flags_out;        // [ld] or null
+    float* goal;               // [3][ld] or null: redrawn for reset vehicles
     StatSlot* slots;           // [grid] or null
     const long long* d_step;   // device step counter (graph launches) or null
     long long t0;              // first global step when d_step is null
@@ -58,6 +59,7 @@ struct ResetArgs {
     const int8_t* mode;
     float* target;
     const uint8_t* mask_in;    // or null: counter-based mask
+    float* goal;               // [3][ld] or null
     uint8_t* mask_out;         // [n]
     int32_t* block_counts;     // [nblocks]
     long long n, ld;
@@ -171,5 +173,29 @@ struct CameraArgs {
 };
 
 const void* depth_kernel();
+
+struct ActArgs {
+    const float* actions;      // [4][act_ld]
+    float* target;             // [4][ld]
+    int8_t* mode;
+    long long n, ld, act_ld;
+    int32_t new_mode;
+    float scale[4], offset[4];
+};
+
+struct TaskArgs {
+    const float* state;        // [13][ld]
+    const float* goal;         // [3][goal_ld]
+    float* obs;                // [13][obs_ld]
+    float* reward;             // [n] or null
+    uint8_t* done;             // [n] or null
+    int32_t* episode;          // [n] or null
+    long long n, ld, goal_ld, obs_ld;
+    int32_t advance, max_steps;
+    float w_v, w_omega, bonus, r_goal, r_far;
+};
+
+const void* actions_kernel();
+const void* observe_kernel();
 
 }  // namespace ag

@@ -173,6 +173,11 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
                         float gx, gy, gz;
                         redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
                         if (C[v].mode == 0) derive_cmd(C[v], 0, gx, gy, gz, 0.0f);
+                        if (a.goal) {
+                            a.goal[idx[v]] = gx;
+                            a.goal[ld + idx[v]] = gy;
+                            a.goal[2 * ld + idx[v]] = gz;
+                        }
                         did_reset[v] = true;
                         if constexpr (OBS) ++c_res;
                     }
@@ -328,6 +333,11 @@ __global__ __launch_bounds__(kResetBlock) void k_reset_mask(ResetArgs a) {
             redraw(s, gx, gy, gz, gi, a.t, a.key0, a.key1, a.lo, a.hi);
 #pragma unroll
             for (int r = 0; r < 13; ++r) a.state[r * a.ld + i] = s[r];
+            if (a.goal) {
+                a.goal[i] = gx;
+                a.goal[a.ld + i] = gy;
+                a.goal[2 * a.ld + i] = gz;
+            }
             if (a.mode[i] == 0) {
                 a.target[i] = gx;
                 a.target[a.ld + i] = gy;
@@ -424,6 +434,47 @@ __global__ __launch_bounds__(256) void k_obstacles(ObstArgs a) {
 }
 
 const void* obstacles_kernel() { return reinterpret_cast<const void*>(&k_obstacles); }
+
+// ---- goal-reaching task: actions in, observation / reward / done out -------
+__global__ __launch_bounds__(256) void k_actions(ActArgs a) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float u = __builtin_amdgcn_fmed3f(a.actions[r * a.act_ld + i], -1.0f, 1.0f);
+        a.target[r * a.ld + i] = a.offset[r] + a.scale[r] * u;
+    }
+    a.mode[i] = (int8_t)a.new_mode;
+}
+
+__global__ __launch_bounds__(256) void k_observe(TaskArgs a) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    float s[13];
+    bool finite = true;
+#pragma unroll
+    for (int r = 0; r < 13; ++r) {
+        s[r] = a.state[r * a.ld + i];
+        finite = finite && isfinite(s[r]);
+    }
+    const float ex = a.goal[i] - s[0], ey = a.goal[a.goal_ld + i] - s[1], ez = a.goal[2 * a.goal_ld + i] - s[2];
+    const float o[13] = {ex, ey, ez, s[3], s[4], s[5], s[6], s[7], s[8], s[9], s[10], s[11], s[12]};
+#pragma unroll
+    for (int r = 0; r < 13; ++r) a.obs[r * a.obs_ld + i] = finite ? o[r] : 0.0f;
+    if (!a.advance) return;
+    const float dist = sqrtf(ex * ex + ey * ey + ez * ez);
+    const float sp = sqrtf(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+    const float wn = sqrtf(s[10] * s[10] + s[11] * s[11] + s[12] * s[12]);
+    const float rew = -dist - a.w_v * sp - a.w_omega * wn + (dist < a.r_goal ? a.bonus : 0.0f);
+    const int ep = a.episode[i] + 1;
+    const bool done = ep >= a.max_steps || dist > a.r_far || !finite;
+    a.reward[i] = finite ? rew : 0.0f;
+    a.done[i] = done ? 1 : 0;
+    a.episode[i] = done ? 0 : ep;
+}
+
+const void* actions_kernel() { return reinterpret_cast<const void*>(&k_actions); }
+const void* observe_kernel() { return reinterpret_cast<const void*>(&k_observe); }
 
 // ---- kernel lookup ---------------------------------------------------------
 // Kernels with trajectories (mode 4) exist for one vehicle per lane and for

@@ -10,7 +10,7 @@ FLAG_NONFINITE, FLAG_SATURATED, FLAG_RESET = 1, 2, 4
 
 EXPORTS = [
     "ag_workspace_size", "ag_create", "ag_destroy", "ag_set_targets", "ag_step", "ag_prepare", "ag_set_exec",
-    "ag_get_exec", "ag_autotune", "ag_reset", "ag_randomize_obstacles", "ag_render_depth", "ag_get_stats", "ag_get_step", "ag_set_step",
+    "ag_get_exec", "ag_autotune", "ag_reset", "ag_randomize_obstacles", "ag_render_depth", "ag_apply_actions", "ag_observe", "ag_get_stats", "ag_get_step", "ag_set_step",
     "ag_rollout_workspace_size", "ag_rollout_forward", "ag_rollout_adjoint", "ag_sync",
     "ag_last_error", "ag_status_string",
 ]
@@ -30,7 +30,8 @@ class Config(C.Structure):
                 ("vparams", C.c_void_p), ("wrench_out", C.c_void_p), ("rotor_out", C.c_void_p),
                 ("flags_out", C.c_void_p), ("reset_prob", C.c_float), ("auto_reset", C.c_int32),
                 ("reset_lo", C.c_float * 3), ("reset_hi", C.c_float * 3),
-                ("collect_stats", C.c_int32), ("autotune_scratch", C.c_int32), ("traj", C.c_void_p)]
+                ("collect_stats", C.c_int32), ("autotune_scratch", C.c_int32), ("traj", C.c_void_p),
+                ("goal", C.c_void_p)]
 
 
 class Exec(C.Structure):
@@ -39,6 +40,11 @@ class Exec(C.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Task(C.Structure):
+    _fields_ = [("w_v", C.c_float), ("w_omega", C.c_float), ("bonus", C.c_float), ("r_goal", C.c_float),
+                ("r_far", C.c_float), ("max_steps", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -78,6 +84,8 @@ def load():
         "ag_randomize_obstacles": ([H, C.c_int32, P, P, P, C.POINTER(C.c_float), C.POINTER(C.c_float), P,
                                     C.c_int64, P, C.c_int64], C.c_int),
         "ag_render_depth": ([H, C.POINTER(Camera), C.c_int32, P, P, C.c_int64, C.c_int64, C.c_int64, P], C.c_int),
+        "ag_apply_actions": ([H, P, C.c_int64, C.c_int32, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
+        "ag_observe": ([H, C.POINTER(Task), C.c_int32, P, C.c_int64, P, P, P], C.c_int),
         "ag_get_stats": ([H, C.POINTER(Stats), C.c_int32], C.c_int),
         "ag_get_step": ([H, C.POINTER(C.c_int64)], C.c_int),
         "ag_set_step": ([H, C.c_int64], C.c_int),

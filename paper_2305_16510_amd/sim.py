@@ -49,7 +49,7 @@ class Sim:
     def __init__(self, groups, state0, mode, target, vparams=None, *, dt=0.01, g=9.81, seed=0,
                  index_base=0, reset_prob=0.0, auto_reset=False, reset_lo=(-5.0, -5.0, -5.0),
                  reset_hi=(5.0, 5.0, 5.0), collect_stats=False, outputs=False,
-                 autotune_scratch=False, traj=None, device="cuda:0"):
+                 autotune_scratch=False, traj=None, goal=None, device="cuda:0"):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("a GPU is required (no CPU fallback)")
@@ -67,6 +67,9 @@ class Sim:
         self.traj = None if traj is None else _dev(traj, F32, self.device)
         if self.traj is not None and self.traj.shape != (L.TRAJ_DIM, self.n):
             raise ValueError("traj [16,n] expected")
+        self.goal = None if goal is None else _dev(goal, F32, self.device)
+        if self.goal is not None and self.goal.shape != (3, self.n):
+            raise ValueError("goal [3,n] expected")
         self.wrench = self.rotors = self.flags = None
         if outputs:
             self.wrench = torch.zeros(L.WRENCH_DIM, self.n, dtype=F32, device=self.device)
@@ -90,6 +93,7 @@ class Sim:
         cfg.collect_stats = int(bool(collect_stats))
         cfg.autotune_scratch = int(bool(autotune_scratch))
         cfg.traj = _ptr(self.traj)
+        cfg.goal = _ptr(self.goal)
         self._cfg = cfg
         nbytes = C.c_size_t(0)
         L.check(self._lib.ag_workspace_size(C.byref(cfg), C.byref(nbytes)), None, "ag_workspace_size")
@@ -212,6 +216,18 @@ class Sim:
                    _ptr(out))
         self._keep = (sh,)
         return out
+
+    def apply_actions(self, actions, mode, scale, offset):
+        """Commands target = offset + scale * clamp(actions, -1, 1) for all vehicles (actions [4, n])."""
+        act = _dev(actions, F32, self.device)
+        self._call("ag_apply_actions", _ptr(act), C.c_int64(int(act.shape[1])), C.c_int32(int(mode)),
+                   (C.c_float * 4)(*scale), (C.c_float * 4)(*offset))
+        self._keep = (act,)
+
+    def observe(self, task, obs, reward=None, done=None, episode=None, advance=True):
+        """Goal-reaching observation [13, n], reward [n], done [n] (uint8), episode counters [n] (int32)."""
+        self._call("ag_observe", C.byref(task), C.c_int32(int(bool(advance))), _ptr(obs),
+                   C.c_int64(int(obs.shape[1])), _ptr(reward), _ptr(done), _ptr(episode))
 
     def stats(self, clear=False):
         s = L.Stats()
