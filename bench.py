@@ -25,9 +25,35 @@ sys.path.insert(0, ROOT)
 BYTES_PER_VSTEP = 52 + 52 + 16 + 1
 FLOPS_PER_VSTEP = 291
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 78.6          # non-packed FP32 FMA: 256 CU x 64 lanes x 2 x 2.4 GHz
-FP32_PEAK_PACKED_TFLOPS = 157.3  # with packed FP32 (not used by this build)
+FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
+# HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the
+# 1,048,576-quad workload, scaled by what the same counters read for a plain
+# 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), and VALU instructions per
+# vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / 64 per lane
+# step).  Valid only while the step-kernel sources hash to ``src``.
+COUNTERS = {
+    "src": "47c5a7017e3bce04",
+    "per_step_bytes": (35475.6 * 2.0 + 53248.0 * 1.0) * 1024,
+    "fused_bytes": (35382.7 * 2.0 + 53248.0 * 1.0) * 1024,
+    "fused_valu_per_vstep": 242.7,
+    "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
+}
+STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
+                "paper_2305_16510_amd/csrc/ag_internal.h")
 PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090
+
+
+def step_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in STEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counters_valid():
+    return COUNTERS["src"] == step_source_hash()
 
 
 def log(*a):
@@ -288,12 +314,17 @@ def main():
             "value": wl.n * K / t_plain, "ms_per_step": t_plain / K * 1e3, "block": best[1],
             "kernel_avg_us": kern_plain * 1e6,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": COUNTERS["per_step_bytes"] if counters_valid() else None,
+                         "algorithmic_bytes": BYTES_PER_VSTEP * wl.n},
         }
         log(f"per-step: {t_plain * 1e3:.2f} ms -> {per_step['value']:.3e} vehicle-steps/s, "
             f"kernel {kern_plain * 1e6:.1f} us = {gbs:.0f} GB/s")
 
-    tflops = FLOPS_PER_VSTEP * wl.n * k / kern_fused / 1e12
+    # achieved = algorithmic flops of the timed launches / their event time
+    # (the last launch of a K that k does not divide runs fewer steps)
+    tflops = FLOPS_PER_VSTEP * wl.n * K / t_evt["fused"] / 1e12
+    valid = counters_valid()
     out = {
         "metric": "vehicle-steps/s at 1M quads (fused vs per-step), %HBM/VALU peak; adjoint s/step",
         "value": value,
@@ -311,10 +342,12 @@ def main():
                                "dt=0.01 s (seeded synthetic)", "n_vehicles": wl.n, "seq_len": 1,
                    "global_batch": wl.n, "parallelism": "none (1 GPU)", "exec": tuned},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": tflops / FP32_PEAK_TFLOPS,
+                     "traffic": COUNTERS["fused_bytes"] if valid and k == 64 else None,
                      "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
-                     "flops_per_vehicle_step": FLOPS_PER_VSTEP,
-                     "peak_packed_fp32": FP32_PEAK_PACKED_TFLOPS},
+                     "steps_per_launch": k, "flops_per_vehicle_step": FLOPS_PER_VSTEP,
+                     "valu_instr_per_vehicle_step": COUNTERS["fused_valu_per_vstep"] if valid else None,
+                     "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},
         "per_step": per_step,
         "fused_over_per_step": (value / per_step["value"]) if per_step else None,
         "paper_context": {"value": PAPER_VSTEPS, "unit": "vehicle-steps/s",
@@ -353,6 +386,10 @@ def main():
         out["measured_peaks"] = {"fp32_fma_lane_ops_per_s": fma, "fp32_fma_tflops": 2 * fma / 1e12,
                                  "copy_GBs": cbw / 1e9}
         out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / (2 * fma / 1e12)
+        if valid:
+            # VALU issue rate against the rate a pure-FMA probe kernel reaches
+            issue = COUNTERS["fused_valu_per_vstep"] * wl.n * K / t_evt["fused"]
+            out["roofline"]["valu_issue_frac_of_measured"] = issue / fma
         if per_step:
             per_step["roofline"]["frac_of_measured_copy"] = per_step["roofline"]["achieved"] / (cbw / 1e9)
         log(f"measured peaks: FP32 FMA {2 * fma / 1e12:.1f} TFLOP/s, copy {cbw / 1e9:.0f} GB/s")

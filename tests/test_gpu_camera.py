@@ -26,14 +26,18 @@ def scene(n, n_obs, seed):
 
 
 def compare(gpu, ref, maxd):
-    """Relative depth error on pixels away from silhouettes (all 4-neighbours
-    within 1% in the oracle's image); edge pixels are counted, not compared."""
+    """Per-pixel relative depth error.  Pixels off by more than 1e-4 may only
+    sit at silhouettes (an oracle neighbour differs by more than 2%), where a
+    grazing ray can hit in one precision and miss in the other.  Returns the
+    largest error, the fraction of mismatched pixels and the number of
+    mismatches away from silhouettes."""
     g = gpu.astype(np.float64)
     pad = np.pad(ref, ((0, 0), (1, 1), (1, 1)), mode="edge")
     nb = np.stack([pad[:, :-2, 1:-1], pad[:, 2:, 1:-1], pad[:, 1:-1, :-2], pad[:, 1:-1, 2:]])
-    smooth = (np.abs(nb - ref[None]) <= 0.01 * ref[None]).all(0)
+    edge = (np.abs(nb - ref[None]) > 0.02 * ref[None]).any(0)
     err = np.abs(g - ref) / np.maximum(ref, 1e-6)
-    return err[smooth].max(), 1.0 - smooth.mean(), (err[~smooth] > 1e-3).mean() if (~smooth).any() else 0.0
+    mism = err > 1e-4
+    return err[~edge].max(), mism.mean(), int((mism & ~edge).sum())
 
 
 def render_case(n, n_obs, W, H, seed, floor=0.0):
@@ -62,11 +66,10 @@ def test_depth_images_match_oracle():
     d, st, ob, shapes, mq = render_case(n, n_obs, W, H, 80)
     ref = raycast.render(st[:, 0:3], st[:, 6:10], np.array([0.1, 0.0, 0.05]), mq, shapes.astype(np.float64),
                          ob, 0.0, W, H, 1.5, 10.0)
-    emax, edge_frac, edge_bad = compare(d, ref, 10.0)
-    print("depth: max rel err off edges %.2e, edge pixels %.2f%%, edge mismatches %.2f%%" %
-          (emax, 100 * edge_frac, 100 * edge_bad))
-    assert emax <= 1e-4
-    assert edge_frac < 0.1
+    emax, mism, off_edge = compare(d, ref, 10.0)
+    print("depth: max rel err off silhouettes %.2e, mismatched pixels %.3f%%, mismatches off silhouettes %d" %
+          (emax, 100 * mism, off_edge))
+    assert emax <= 1e-4 and mism < 0.005 and off_edge == 0
     assert ((ref < 10.0).mean() > 0.2) and ((ref == 10.0).mean() > 0.01)
 
 
@@ -79,6 +82,6 @@ def test_full_resolution_sampled_cameras():
     idx = np.array([0, 333, 700, 1023])
     ref = raycast.render(st[idx, 0:3], st[idx, 6:10], np.array([0.1, 0.0, 0.05]), mq, shapes.astype(np.float64),
                          ob[idx], 0.0, W, H, 1.5, 10.0)
-    emax, edge_frac, _ = compare(d[idx], ref, 10.0)
-    print("full res: max rel err off edges %.2e, edge pixels %.2f%%" % (emax, 100 * edge_frac))
-    assert emax <= 1e-4 and edge_frac < 0.1
+    emax, mism, off_edge = compare(d[idx], ref, 10.0)
+    print("full res: max rel err off silhouettes %.2e, mismatched pixels %.3f%%" % (emax, 100 * mism))
+    assert emax <= 1e-4 and mism < 0.005 and off_edge == 0
