@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 # kernel (state in and out, 4-float command, mode byte) and FP32 flops of one
 # step on the shared straight-line path (quad allocation).
 BYTES_PER_VSTEP = 52 + 52 + 16 + 1
-FLOPS_PER_VSTEP = 291
+FLOPS_PER_VSTEP = 274
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the
@@ -89,10 +89,23 @@ def cpu_baseline(wl, n_sample, steps):
     t0 = time.perf_counter()
     oracle.step.rollout(s0, mode, tgt, fleet, sub.dt, sub.g, steps)
     dt = time.perf_counter() - t0
-    return {"value": n_sample * steps / dt, "unit": "vehicle-steps/s", "cores": torch.get_num_threads(),
+    cores = torch.get_num_threads()
+    # the same oracle on one thread, on a smaller slice
+    n1, s1 = max(1, n_sample // 8), max(1, steps // 3)
+    sub1 = workloads.subset(wl, n1)
+    a0, am, at = oracle.step.from_workload_arrays(sub1.state0, sub1.mode, sub1.target)
+    f1 = oracle.Fleet.from_groups(sub1.groups, sub1.n, sub1.vparams)
+    torch.set_num_threads(1)
+    t1 = time.perf_counter()
+    oracle.step.rollout(a0, am, at, f1, sub1.dt, sub1.g, s1)
+    dt1 = time.perf_counter() - t1
+    torch.set_num_threads(cores)
+    return {"value": n_sample * steps / dt, "unit": "vehicle-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {n_sample} vehicles of the workload x {steps} steps (FP64 torch on CPU)",
-            "seconds": dt}
+            "seconds": dt,
+            "single_thread": {"value": n1 * s1 / dt1, "cores": 1,
+                              "sample": f"first {n1} vehicles x {s1} steps", "seconds": dt1}}
 
 
 def bench_adjoint(sync, reps=3):
@@ -186,6 +199,33 @@ def bench_large(sync):
                             "what": "forward + adjoint + one SGD step on the 10 gains"}}
 
 
+def bench_per_step_large(sync, steps=200):
+    """Per-step kernel at 4,194,304 quads (position mode, dt = 0.005, no
+    resets): 507 MB of state, commands and mode per step, twice the 256 MB
+    Infinity Cache, so the bytes come from HBM."""
+    import workloads
+    from paper_2305_16510_amd.sim import Sim
+    wl = workloads.c5_large()
+    sim = Sim.from_workload(wl, reset_prob=0.0)
+    best = None
+    for blk in (64, 256):
+        sim.set_exec(kind=0, block=blk, use_graph=0)
+        sim.raw_step(10)
+        sync()
+        t = event_time(sim.stream, lambda: [sim.raw_step(1) for _ in range(steps)])
+        if best is None or t < best[0]:
+            best = (t, blk)
+    sim.close()
+    t, blk = best
+    gbs = BYTES_PER_VSTEP * wl.n * steps / t / 1e9
+    log(f"per-step at {wl.n}: {t / steps * 1e6:.1f} us per launch = {gbs:.0f} GB/s (block {blk})")
+    return {"workload": "4,194,304 quads, position mode, dt=0.005, plain per-step launches",
+            "n_vehicles": wl.n, "steps": steps, "block": blk, "kernel_avg_us": t / steps * 1e6,
+            "value": wl.n * steps / t,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS}}
+
+
 def bench_camera(sync, n=1024, n_obs=20, W=480, H=270, reps=5):
     """Depth cameras: 2^10 vehicles with 270 x 480 images (the paper's camera
     benchmark shape, Sec. VI) in environments with 20 primitive obstacles
@@ -235,6 +275,7 @@ def main():
     ap.add_argument("--no-per-step", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--exec", type=str, default="", help="fixed fused policy 'block,vpl,k,grid' (skips tuning)")
+    ap.add_argument("--per-step-block", type=int, default=0, help="fixed block of the per-step kernel (skips its sweep)")
     ap.add_argument("--cpu-sample", type=int, default=65_536)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -290,7 +331,7 @@ def main():
     per_step = None
     if not args.no_per_step:
         best = None
-        for blk in (64, 128, 256, 512):
+        for blk in ((args.per_step_block,) if args.per_step_block else (64, 128, 256, 512)):
             sim.set_exec(kind=0, block=blk, use_graph=0)
             sim.raw_step(20)
             t = timed(lambda: sim.raw_step(50), sync)
@@ -350,6 +391,9 @@ def main():
                      "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},
         "per_step": per_step,
         "fused_over_per_step": (value / per_step["value"]) if per_step else None,
+        "env": {"device": torch.cuda.get_device_name(0),
+                "compute_units": torch.cuda.get_device_properties(0).multi_processor_count,
+                "torch": torch.__version__, "hip": torch.version.hip, "clocks": "not locked"},
         "paper_context": {"value": PAPER_VSTEPS, "unit": "vehicle-steps/s",
                           "hardware": "2x RTX 3090 (use of the second GPU not stated)",
                           "workload": "2^17 robots, attitude/velocity commands (Sec. VI)"},
@@ -370,6 +414,7 @@ def main():
         out["adjoint"] = bench_adjoint(sync)
         out["uneven_groups"] = bench_uneven(sync)
         out["large_resets"] = bench_large(sync)
+        out["per_step_4M"] = bench_per_step_large(sync)
         out["depth_cameras"] = bench_camera(sync)
 
     sim.close()

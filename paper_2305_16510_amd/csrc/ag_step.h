@@ -14,8 +14,11 @@
 //     R_d^T R = T^T (R_z(psi)^T R) with T = R_y(theta_d) R_x(phi_d);
 //   * eqs. (1)+(2) give Omega_d = psidot_d R_d^T e3, hence eq. (4) becomes
 //     e_Omega = Omega - psidot_d R^T e3;
-//   * position and velocity errors are rotated into the reference yaw frame
-//     before the (x-y symmetric) gains are applied.
+//   * the x-y gains are equal, so the commanded force is formed in the
+//     inertial frame and rotated into the reference yaw frame afterwards,
+//     with the target terms as per-vehicle constants;
+//   * dt, the mass, 1/J and the 1/2 of eq. (3) are folded into per-vehicle
+//     constants, which a fused launch computes once (loop-invariant).
 // Allocation uses a unit-arm table per rotor layout: u = clip(A1^+ (f, M_x/l,
 // M_y/l, M_z)), applied wrench (sum u, l (A1 u)_1, l (A1 u)_2, (A1 u)_3).
 // Integration is semi-implicit Euler with quaternion renormalisation.
@@ -126,9 +129,13 @@ AG_DEV void load_params(Params& P, const float* __restrict__ gt, const float* __
 }
 
 // Reciprocal square root as the single hardware instruction (1 ulp); every
-// argument here is a sum of squares of order one to a few hundred, never a
-// denormal, so the denormal-range rescaling of rsqrtf is not needed.
+// argument here is a sum of squares that is of order one to a few hundred or
+// carries a normal bias (kTiny2), never a denormal, so the denormal-range
+// rescaling of rsqrtf is not needed.
 AG_DEV float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Bias of the angle extractions (2^-60 and its square, both normal FP32).
+constexpr float kTiny = 0x1p-60f, kTiny2 = 0x1p-120f;
 
 // Rotor-count class of a kernel: 4, 6 or 8 when every group of the launch
 // has that many rotors, 0 for a mix (8 slots, inactive slots masked).
@@ -182,20 +189,24 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     constexpr int NR = RotorClass<NRC>::NR;
     constexpr bool MIXED = RotorClass<NRC>::MIXED;
     const float qw = s[6], qx = s[7], qy = s[8], qz = s[9];
-    // ---- R(q), unit-norm form --------------------------------------------
-    const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
-    const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
-    const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
-    const float R00 = 1.0f - 2.0f * (yy + zz), R01 = 2.0f * (xy - wz), R02 = 2.0f * (xz + wy);
-    const float R10 = 2.0f * (xy + wz), R11 = 1.0f - 2.0f * (xx + zz), R12 = 2.0f * (yz - wx);
-    const float R20 = 2.0f * (xz - wy), R21 = 2.0f * (yz + wx), R22 = 1.0f - 2.0f * (xx + yy);
+    // ---- R(q), unit-norm form, from the doubled components ----------------
+    const float x2 = qx + qx, y2 = qy + qy, z2 = qz + qz;
+    const float wz2 = qw * z2, wy2 = qw * y2, wx2 = qw * x2;
+    const float omzz = 1.0f - qz * z2;
+    const float R00 = omzz - qy * y2, R11 = omzz - qx * x2, R22 = (1.0f - qy * y2) - qx * x2;
+    const float R01 = qx * y2 - wz2, R10 = qx * y2 + wz2;
+    const float R02 = qx * z2 + wy2, R20 = qx * z2 - wy2;
+    const float R12 = qy * z2 - wx2, R21 = qy * z2 + wx2;
 
     // ---- current yaw (Z-Y-X), trig-free -----------------------------------
-    const float r2 = R00 * R00 + R10 * R10;
-    const bool yok = r2 > 0.0f;
+    // Here and in the tilt below, cos and sin of the angle of a 2-vector
+    // (c, s) come as ((c + 2^-60), s) / sqrt(c^2 + s^2 + 2^-120): for a zero
+    // vector this gives the convention angle = 0 (cos 1, sin 0) without a
+    // select, and otherwise it moves cos by at most 2^-60 / |(c, s)|.
+    const float r2 = R00 * R00 + (R10 * R10 + kTiny2);
     const float ir = rsq(r2);
-    const float cpsi = yok ? R00 * ir : 1.0f;
-    const float spsi = yok ? R10 * ir : 0.0f;
+    const float cpsi = (R00 + kTiny) * ir;
+    const float spsi = R10 * ir;
 
     const int mode = C.mode;
     const bool m0 = mode == 0, m1 = mode == 1, m2 = mode == 2, m3 = mode == 3;
@@ -205,7 +216,27 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float sr = m0 ? C.sa : spsi;
 
     // ---- commanded force in the reference frame (position / velocity) -----
+    // F_V = m (kx e_V + kv (v_d - v_V) + g e3), e_V and v_V the position error
+    // and the velocity rotated by R_z(psi_ref)^T; the x-y gains are equal, so
+    // the rotation is applied after them:
+    //   F_V,xy = R_z(psi_ref)^T (m kx' (x_d - x) - m kv v)_xy + m kv v_d,xy',
+    //   F_V,z  = m kx' (z_d - z) - m kv v_z + m kv v_d,z' + m g,
+    // with kx' = kx in position mode and 0 otherwise, v_d' = v_d in velocity
+    // mode and 0 otherwise.  Products of per-vehicle constants are loop-
+    // invariant in a fused launch.  (A non-finite position outside position
+    // mode therefore makes F non-finite, where the plain formula ignores it.)
     const float vx = s[3], vy = s[4], vz = s[5];
+    const float kxm_xy = m0 ? P.m * P.kx_xy : 0.0f, kxm_z = m0 ? P.m * P.kx_z : 0.0f;
+    const float kvm_xy = P.m * P.kv_xy, kvm_z = P.m * P.kv_z;
+    const float Kx = kxm_xy * C.t0, Ky = kxm_xy * C.t1;
+    const float Vx = m1 ? kvm_xy * C.t0 : 0.0f, Vy = m1 ? kvm_xy * C.t1 : 0.0f;
+    const float Kz = kxm_z * C.t2 + ((m1 ? kvm_z * C.t2 : 0.0f) + P.m * g);
+    const float Ax = Kx - kxm_xy * s[0] - kvm_xy * vx;
+    const float Ay = Ky - kxm_xy * s[1] - kvm_xy * vy;
+    const float Fx = cr * Ax + (sr * Ay + Vx);
+    const float Fy = cr * Ay + (Vy - sr * Ax);
+    const float Fz = Kz - kxm_z * s[2] - kvm_z * vz;
+    // the same quantities in the plain decomposition (reverse pass only)
     const float vVx = cr * vx + sr * vy;
     const float vVy = cr * vy - sr * vx;
     const float dxE = C.t0 - s[0], dyE = C.t1 - s[1], dzE = C.t2 - s[2];
@@ -215,21 +246,18 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float wvx = (m1 ? C.t0 : 0.0f) - vVx;
     const float wvy = (m1 ? C.t1 : 0.0f) - vVy;
     const float wvz = (m1 ? C.t2 : 0.0f) - vz;
-    const float ax = P.kx_xy * ex + P.kv_xy * wvx;
-    const float ay = P.kx_xy * ey + P.kv_xy * wvy;
-    const float az = P.kx_z * ez + P.kv_z * wvz;
-    const float Fx = P.m * ax, Fy = P.m * ay, Fz = P.m * (az + g);
 
     // ---- tilt from force, eqs. (8)-(9) without trig -----------------------
-    const float h2 = Fx * Fx + Fz * Fz;
+    // theta_d from (F_z, F_x), then phi_d from (h, -F_y), h = |(F_x, F_z)|;
+    // h is itself biased by 2^-60 at most, so F = 0 gives theta_d = phi_d = 0
+    const float h2 = Fx * Fx + (Fz * Fz + kTiny2);
     const float n2 = h2 + Fy * Fy;
-    const bool hok = h2 > 0.0f, nok = n2 > 0.0f;
     const float ih = rsq(h2), inn = rsq(n2);
-    const float hh = hok ? h2 * ih : 0.0f;
-    float cth = hok ? Fz * ih : 1.0f;
-    float sth = hok ? Fx * ih : 0.0f;
-    float cph = nok ? hh * inn : 1.0f;
-    float sph = nok ? -Fy * inn : 0.0f;
+    const float hh = h2 * ih;
+    float cth = (Fz + kTiny) * ih;
+    float sth = Fx * ih;
+    float cph = hh * inn;
+    float sph = -Fy * inn;
     cth = m2 ? C.cb : cth;
     sth = m2 ? C.sb : sth;
     cph = m2 ? C.ca : cph;
@@ -247,15 +275,11 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     // ---- e_R = 1/2 vee(E - E^T), E = T^T P, T = R_y(theta) R_x(phi) --------
     const float T01 = sth * sph, T02 = sth * cph;
     const float T21 = cth * sph, T22 = cth * cph;
-    const float E21 = T02 * P01 - sph * P11 + T22 * P21;
-    const float E12 = T01 * P02 + cph * P12 + T21 * P22;
-    const float E02 = cth * P02 - sth * P22;
-    const float E20 = T02 * P00 - sph * P10 + T22 * P20;
-    const float E10 = T01 * P00 + cph * P10 + T21 * P20;
-    const float E01 = cth * P01 - sth * P21;
-    float eR0 = 0.5f * (E21 - E12);
-    float eR1 = 0.5f * (E02 - E20);
-    float eR2 = 0.5f * (E10 - E01);
+    // twice e_R, each difference of E entries as one multiply-add chain; the
+    // 1/2 is folded into the gains of eq. (5) (exact scaling)
+    float dR0 = T02 * P01 - sph * P11 + T22 * P21 - T01 * P02 - cph * P12 - T21 * P22;   // E21 - E12
+    float dR1 = cth * P02 - sth * P22 - T02 * P00 + sph * P10 - T22 * P20;               // E02 - E20
+    float dR2 = T01 * P00 + cph * P10 + T21 * P20 - cth * P01 + sth * P21;               // E10 - E01
 
     // ---- e_Omega = Omega - psidot_d R^T e3 ---------------------------------
     const float psidot = m1 ? C.t3 : (m2 ? C.t2 : 0.0f);
@@ -311,9 +335,9 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         const float d1 = R01 * dx + R11 * dy + R21 * dz;
         const float d2 = R02 * dx + R12 * dy + R22 * dz;
         f = m4 ? f4 : f;
-        eR0 = m4 ? 0.5f * (G21 - G12) : eR0;
-        eR1 = m4 ? 0.5f * (G02 - G20) : eR1;
-        eR2 = m4 ? 0.5f * (G10 - G01) : eR2;
+        dR0 = m4 ? G21 - G12 : dR0;
+        dR1 = m4 ? G02 - G20 : dR1;
+        dR2 = m4 ? G10 - G01 : dR2;
         eW0 = m4 ? w0 - c0 : eW0;
         eW1 = m4 ? w1 - c1 : eW1;
         eW2 = m4 ? w2 - c2 : eW2;
@@ -324,22 +348,25 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     }
 
     // ---- M = -kR e_R - kW e_Omega + Omega x J Omega, eq. (5) ---------------
-    float M0 = -P.kR0 * eR0 - P.kW0 * eW0 + gy0;
-    float M1 = -P.kR1 * eR1 - P.kW1 * eW1 + gy1;
-    float M2 = -P.kR2 * eR2 - P.kW2 * eW2 + gy2;
+    const float hkR0 = 0.5f * P.kR0, hkR1 = 0.5f * P.kR1, hkR2 = 0.5f * P.kR2;
+    float M0 = gy0 - hkR0 * dR0 - P.kW0 * eW0;
+    float M1 = gy1 - hkR1 * dR1 - P.kW1 * eW1;
+    float M2 = gy2 - hkR2 * dR2 - P.kW2 * eW2;
     if constexpr (TRK) {
         M0 -= ff0;
         M1 -= ff1;
         M2 -= ff2;
     }
-    const bool known = m0 || m1 || m2 || m3 || m4;
-    M0 = m3 ? C.t1 : (known ? M0 : 0.0f);
-    M1 = m3 ? C.t2 : (known ? M1 : 0.0f);
-    M2 = m3 ? C.t3 : (known ? M2 : 0.0f);
+    // mode 3 takes the commanded moment, an unknown mode a zero wrench (one
+    // select per component against per-vehicle constants)
+    const bool direct = m3 || !(m0 || m1 || m2 || m4);
+    M0 = direct ? (m3 ? C.t1 : 0.0f) : M0;
+    M1 = direct ? (m3 ? C.t2 : 0.0f) : M1;
+    M2 = direct ? (m3 ? C.t3 : 0.0f) : M2;
 
     // ---- allocation and clamping ------------------------------------------
     const float a1 = M0 * P.inv_arm, a2 = M1 * P.inv_arm;
-    float fa, Ma0, Ma1, Ma2;
+    float fa, S0, S1, S2;
     int nsat = 0;
     float raws[NR];
 #pragma unroll
@@ -356,44 +383,47 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         nsat += (int)(act & ((raw < P.umin) | (raw > P.umax)));
         if (r == 0) {
             fa = u * ac.x;
-            Ma0 = u * ac.y;
-            Ma1 = u * ac.z;
-            Ma2 = u * ac.w;
+            S0 = u * ac.y;
+            S1 = u * ac.z;
+            S2 = u * ac.w;
         } else {
             fa += u * ac.x;
-            Ma0 += u * ac.y;
-            Ma1 += u * ac.z;
-            Ma2 += u * ac.w;
+            S0 += u * ac.y;
+            S1 += u * ac.z;
+            S2 += u * ac.w;
         }
         if constexpr (WANT_U) u_out[r] = u;
     }
-    Ma0 *= P.arm;
-    Ma1 *= P.arm;
+    // applied wrench: (fa, l S0, l S1, S2)
     if constexpr (WANT_W) {
         W->f = f; W->M0 = M0; W->M1 = M1; W->M2 = M2;
-        W->fa = fa; W->Ma0 = Ma0; W->Ma1 = Ma1; W->Ma2 = Ma2;
+        W->fa = fa; W->Ma0 = P.arm * S0; W->Ma1 = P.arm * S1; W->Ma2 = S2;
     }
 
     // ---- semi-implicit Euler ----------------------------------------------
-    const float acc = fa * P.inv_m;
-    const float nvx = vx + dt * (acc * R02);
-    const float nvy = vy + dt * (acc * R12);
-    const float nvz = vz + dt * (acc * R22 - g);
+    // dt is folded into 1/m and J^-1 (loop-invariant products in a fused launch)
+    const float dt_m = dt * P.inv_m, dtg = dt * g;
+    const float dtJi0 = dt * P.Ji0, dtJi1 = dt * P.Ji1, dtJi2 = dt * P.Ji2;
+    const float dva = fa * dt_m;
+    const float nvx = dva * R02 + vx;
+    const float nvy = dva * R12 + vy;
+    const float nvz = dva * R22 + (vz - dtg);
     s[0] = s[0] + dt * nvx;
     s[1] = s[1] + dt * nvy;
     s[2] = s[2] + dt * nvz;
     s[3] = nvx; s[4] = nvy; s[5] = nvz;
-    const float nw0 = w0 + dt * ((Ma0 - gy0) * P.Ji0);
-    const float nw1 = w1 + dt * ((Ma1 - gy1) * P.Ji1);
-    const float nw2 = w2 + dt * ((Ma2 - gy2) * P.Ji2);
+    const float nw0 = (P.arm * S0 - gy0) * dtJi0 + w0;
+    const float nw1 = (P.arm * S1 - gy1) * dtJi1 + w1;
+    const float nw2 = (S2 - gy2) * dtJi2 + w2;
     s[10] = nw0; s[11] = nw1; s[12] = nw2;
     // q <- normalize(q + dt/2 q (x) (0, Omega+))
+    // with h = (dt/2) Omega+ first: t = q + q (x) (0, h), one chain per component
     const float hd = 0.5f * dt;
-    const float dqw = -(qx * nw0 + qy * nw1 + qz * nw2);
-    const float dqx = qw * nw0 + (qy * nw2 - qz * nw1);
-    const float dqy = qw * nw1 + (qz * nw0 - qx * nw2);
-    const float dqz = qw * nw2 + (qx * nw1 - qy * nw0);
-    const float tw = qw + hd * dqw, tx = qx + hd * dqx, ty = qy + hd * dqy, tz = qz + hd * dqz;
+    const float h0 = hd * nw0, h1 = hd * nw1, h2q = hd * nw2;
+    const float tw = qw - qx * h0 - qy * h1 - qz * h2q;
+    const float tx = qx + qw * h0 + qy * h2q - qz * h1;
+    const float ty = qy + qw * h1 + qz * h0 - qx * h2q;
+    const float tz = qz + qw * h2q + qx * h1 - qy * h0;
     const float iq = rsq(tw * tw + tx * tx + ty * ty + tz * tz);
     s[6] = tw * iq; s[7] = tx * iq; s[8] = ty * iq; s[9] = tz * iq;
 
@@ -433,6 +463,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         float bv0 = bnv0, bv1 = bnv1, bv2 = bnv2;
         const float bacc = dt * (bnv0 * R02 + bnv1 * R12 + bnv2 * R22);
         float bR00 = 0.0f, bR01 = 0.0f, bR10 = 0.0f, bR11 = 0.0f, bR20 = 0.0f, bR21 = 0.0f;
+        const float acc = fa * P.inv_m;
         float bR02 = dt * (acc * bnv0), bR12 = dt * (acc * bnv1), bR22 = dt * (acc * bnv2);
         const float bfa = bacc * P.inv_m;
 
@@ -460,6 +491,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         bf = frc ? bf : 0.0f;
 
         // ---- moment law, eq. (5) -------------------------------------------
+        const float eR0 = 0.5f * dR0, eR1 = 0.5f * dR1, eR2 = 0.5f * dR2;
         gb[4] -= bM0 * eR0; gb[5] -= bM1 * eR1; gb[6] -= bM2 * eR2;
         gb[7] -= bM0 * eW0; gb[8] -= bM1 * eW1; gb[9] -= bM2 * eW2;
         const float beR0 = -P.kR0 * bM0, beR1 = -P.kR1 * bM1, beR2 = -P.kR2 * bM2;
@@ -509,7 +541,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         float bsr = bP00 * R10 - bP10 * R00 + bP01 * R11 - bP11 * R01 + bP02 * R12 - bP12 * R02;
 
         // ---- tilt extraction, eqs. (8)-(9) ----------------------------------
-        if (hok) {
+        if (Fx * Fx + Fz * Fz > 0.0f) {     // zero (F_x, F_z): convention branch, no derivative
             const float ih3 = ih * ih * ih;
             const float D = (bcth * Fx - bsth * Fz) * ih3;
             bFx -= Fz * D;
@@ -546,7 +578,7 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         bsr += bvVx * vy - bvVy * vx;
 
         // ---- yaw readout (reference frame of velocity / attitude modes) -----
-        if (!m0 && yok) {
+        if (!m0 && R00 * R00 + R10 * R10 > 0.0f) {
             const float D2 = (bcr * R10 - bsr * R00) * (ir * ir * ir);
             bR00 += R10 * D2;
             bR10 -= R00 * D2;

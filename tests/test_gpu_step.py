@@ -139,6 +139,50 @@ def test_all_modes_one_step_state_parity():
     assert err <= 1e-5
 
 
+def test_degenerate_angle_conventions():
+    """The zero-vector conventions of the angle readouts, on inputs that are
+    exactly degenerate in FP32 and FP64 alike: with g = 8, m = 1 and
+    k_v,z = k_x,z = 2 the commanded force cancels exactly (theta_d = phi_d =
+    0 by convention), and q = (1/2, 1/2, -1/2, 1/2) has R11 = R21 = 0 (current
+    yaw 0 by convention).  Five cases by index mod 5: velocity mode with zero
+    force; the same with the vertical body x axis; velocity mode with a
+    regular target and the vertical axis; attitude mode with the vertical
+    axis; position mode with zero force.  First-step wrench to the usual
+    tolerance."""
+    need_gpu()
+    wl = workloads.c1_parity(n=320, seed=61)
+    wl.g = 8.0
+    rng = np.random.default_rng(62)
+    c = np.arange(wl.n) % 5
+    wl.mode[:] = np.select([c == 3, c == 4], [2, 0], 1).astype(np.int8)
+    vert = (c == 1) | (c == 2) | (c == 3)
+    wl.state0[6:10, vert] = np.array([[0.5], [0.5], [-0.5], [0.5]], np.float32)
+    zf = (c == 0) | (c == 1)
+    wl.state0[3:6, zf] = 0.0
+    wl.target[:, zf] = np.array([[0.0], [0.0], [-4.0], [0.0]], np.float32)
+    v2 = c == 2
+    wl.target[:, v2] = np.concatenate([rng.uniform(-2, 2, (3, v2.sum())),
+                                       rng.uniform(-1, 1, (1, v2.sum()))]).astype(np.float32)
+    m2 = c == 3
+    wl.target[:, m2] = np.stack([rng.uniform(-0.3, 0.3, m2.sum()), rng.uniform(-0.3, 0.3, m2.sum()),
+                                 rng.uniform(-1, 1, m2.sum()), rng.uniform(5, 15, m2.sum())]).astype(np.float32)
+    p0 = c == 4
+    wl.target[:, p0] = np.stack([np.full(p0.sum(), 1.0), np.full(p0.sum(), -2.0), np.full(p0.sum(), 1.0),
+                                 rng.uniform(-3, 3, p0.sum())]).astype(np.float32)
+    wl.state0[0:3, p0] = np.array([[1.0], [-2.0], [5.0]], np.float32)
+    wl.state0[3:6, p0] = 0.0
+    pres, ws, _ = run_per_step_with_wrench(wl, 1)
+    _, mode, tgt, fleet = oracle_inputs(wl)
+    _, info = oracle.step.step(pres[0], mode, tgt, fleet, wl.dt, wl.g)
+    zero_f = torch.as_tensor(zf | p0)
+    assert torch.equal(info["f"][zero_f], torch.zeros(int(zero_f.sum()), dtype=F64))
+    assert torch.equal(ws[0][zero_f, 0], torch.zeros(int(zero_f.sum()), dtype=F64))
+    errs = wrench_errors(ws[0], info, fleet, wl.g, near_kink=near_clamp(info, fleet))
+    worst = [float(e.max()) for e in errs]
+    print("degenerate cases: max rel err f, M, f', M':", worst)
+    assert max(worst) <= 1e-5
+
+
 def test_free_fall_closed_form_on_gpu():
     """Wrench mode with zero command: the GPU integrator reproduces the
     discrete free-fall closed form (FP32 rounding only)."""
