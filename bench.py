@@ -32,10 +32,10 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / 64 per lane
 # step).  Valid only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "47c5a7017e3bce04",
-    "per_step_bytes": (35475.6 * 2.0 + 53248.0 * 1.0) * 1024,
-    "fused_bytes": (35382.7 * 2.0 + 53248.0 * 1.0) * 1024,
-    "fused_valu_per_vstep": 242.7,
+    "src": "39beb8c922dc7952",
+    "per_step_bytes": (35895.7 * 2.0 + 53248.0 * 1.0) * 1024,
+    "fused_bytes": (35386.8 * 2.0 + 53248.0 * 1.0) * 1024,
+    "fused_valu_per_vstep": 191.9,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
