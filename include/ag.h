@@ -277,9 +277,12 @@ ag_status ag_set_step(ag_handle h, int64_t step);
  * modified).  Requires position or wrench modes and per-vehicle vparams.
  * Forward: per-vehicle loss (loss_out [n], without scale_n) and checkpoints
  * of the state every ckpt_every steps in `ws`; final_state optional [13][ld].
- * Adjoint: recomputes each checkpoint segment and sweeps it backwards,
- * writing dL/dgains (dgains [10][ld]) and dL/dx0 (dx0 [13][ld]) multiplied by
- * `seed_grad`; both calls must use the same arguments and workspace. */
+ * Adjoint: recomputes each checkpoint segment (into one of two tape buffers
+ * in `ws`, overlapped with the reverse sweep of the later segment) and sweeps
+ * it backwards, writing dL/dgains (dgains [10][ld]) and dL/dx0 (dx0 [13][ld])
+ * multiplied by `seed_grad`; both calls must use the same arguments and
+ * workspace.  Workspace: n_ckpt + 2 ckpt_every states of 13 floats per
+ * vehicle, n_ckpt = ceil(n_steps / ckpt_every), each part 256-byte aligned. */
 ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_every, size_t* bytes);
 ag_status ag_rollout_forward(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every,
                              float w_omega, void* ws, size_t ws_bytes, float* loss_out,

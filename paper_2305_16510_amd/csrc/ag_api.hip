@@ -891,7 +891,7 @@ ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_e
     const long long n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
     size_t off = 0;
     off = align_up(off + (size_t)n_ckpt * AG_STATE_DIM * n * sizeof(float));
-    off = align_up(off + (size_t)ckpt_every * AG_STATE_DIM * n * sizeof(float));
+    off = align_up(off + 2 * (size_t)ckpt_every * AG_STATE_DIM * n * sizeof(float));   // two tape buffers
     *bytes = off;
     return AG_OK;
 }
@@ -970,7 +970,8 @@ ag_status ag_rollout_adjoint(ag_handle h, const float* x0, int32_t n_steps, int3
     a.dgains = dgains;
     a.dx0 = dx0;
     a.seed_grad = seed_grad / (float)h->cfg.n;
-    return launch(h, rollout_adj_kernel(h->nr_class), s.grid, s.block, s.shmem, &a);
+    // two wavefronts per 64 vehicles: reverse sweep and recomputation
+    return launch(h, rollout_adj_kernel(h->nr_class), s.grid, dim3(2 * kRolloutBlock), s.shmem, &a);
 }
 
 ag_status ag_sync(ag_handle h) {

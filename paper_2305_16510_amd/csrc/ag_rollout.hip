@@ -4,14 +4,18 @@
 // function of the simulator, accumulates its loss
 //   l_i = sum_{t=1..T} |x_t - goal|^2 + w_omega |Omega_t|^2
 // and writes the state every m steps to a checkpoint array.
-// Adjoint: for each checkpoint segment, last to first, the lane recomputes
-// the segment's states into a per-vehicle tape (structure-of-arrays in the
-// caller's workspace), then walks the tape backwards running the hand-
-// written reverse of each step (step_core<..., GRAD = true>), which adds the
-// loss gradient of the post-step state and pulls the adjoint back to the
-// pre-step state while accumulating the gain adjoints.  Vehicles are
-// independent, so the whole rollout of a vehicle stays in one lane: no
-// synchronisation beyond the LDS staging of the group tables.
+// Adjoint: the segments between checkpoints are handled last to first.  A
+// segment's states are recomputed from its checkpoint into a tape (structure-
+// of-arrays in the caller's workspace), then the tape is walked backwards
+// running the hand-written reverse of each step (step_core<..., GRAD = true>),
+// which adds the loss gradient of the post-step state and pulls the adjoint
+// back to the pre-step state while accumulating the gain adjoints.  A block
+// holds 64 vehicles and two wavefronts: while wavefront 0 sweeps segment s
+// backwards from tape buffer s & 1, wavefront 1 recomputes segment s - 1 into
+// the other buffer, and a block barrier separates the segments.  With one
+// vehicle per lane the reverse sweep alone is latency-bound (the 65,536-
+// vehicle workload fills one wavefront per SIMD), so the recomputation runs
+// in the issue slots it leaves idle.
 #include <hip/hip_runtime.h>
 
 #include "ag.h"
@@ -29,11 +33,10 @@ __device__ __forceinline__ int rollout_find_group(const int32_t* __restrict__ go
     return lo;
 }
 
-// Stage the groups overlapping this block's vehicles; returns the vehicle's group entry.
+// Stage the groups overlapping vehicles [base, end) (every thread of the
+// block calls it); returns the group entry of vehicle i.
 __device__ __forceinline__ const float* rollout_stage(const RolloutArgs& a, float* lds, int* loff, int* sh,
-                                                      long long i) {
-    const long long base = (long long)blockIdx.x * blockDim.x;
-    const long long end = base + blockDim.x < a.n ? base + blockDim.x : a.n;
+                                                      long long base, long long end, long long i) {
     if (threadIdx.x == 0) {
         const int glo = a.n_groups == 1 ? 0 : rollout_find_group(a.goff, a.n_groups, base);
         const int ghi = a.n_groups == 1 ? 0 : rollout_find_group(a.goff, a.n_groups, end - 1);
@@ -56,8 +59,9 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     float* lds = reinterpret_cast<float*>(lds4);
     int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
     __shared__ int sh[2];
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const float* gt = rollout_stage(a, lds, loff, sh, i);
+    const long long base = (long long)blockIdx.x * blockDim.x;
+    const long long i = base + threadIdx.x;
+    const float* gt = rollout_stage(a, lds, loff, sh, base, base + blockDim.x < a.n ? base + blockDim.x : a.n, i);
     if (i >= a.n) return;
     const long long ld = a.ld, n = a.n;
     float s[13];
@@ -87,20 +91,75 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     }
 }
 
+// Recompute segment seg from its checkpoint: tape entry t - t0 = state before step t.
 template <int NR>
-__global__ __launch_bounds__(256) void k_rollout_adj(RolloutArgs a) {
+__device__ __forceinline__ void recompute_segment(const RolloutArgs& a, const Params& P, const Cmd& C,
+                                                  const float* gt, int seg, float* tape, long long i) {
+    const long long n = a.n;
+    const int t0 = seg * a.m;
+    const int t1 = t0 + a.m < a.T ? t0 + a.m : a.T;
+    const float* ck = a.ckpt + (long long)seg * 13 * n;
+    float s[13];
+#pragma unroll
+    for (int r = 0; r < 13; ++r) s[r] = ck[r * n + i];
+    for (int t = t0; t < t1; ++t) {
+        float* tp = tape + (long long)(t - t0) * 13 * n;
+#pragma unroll
+        for (int r = 0; r < 13; ++r) tp[r * n + i] = s[r];
+        if (t + 1 < t1) step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+    }
+}
+
+// Reverse sweep of segment seg over its tape; the next (earlier) tape entry is
+// loaded while the current step's reverse runs, hiding the load latency.
+template <int NR>
+__device__ __forceinline__ void reverse_segment(const RolloutArgs& a, const Params& P, const Cmd& C,
+                                                const float* gt, int seg, const float* tape, long long i, Adj& A) {
+    const long long n = a.n;
+    const int t0 = seg * a.m;
+    const int t1 = t0 + a.m < a.T ? t0 + a.m : a.T;
+    float s[13], nxt[13];
+    {
+        const float* tp = tape + (long long)(t1 - 1 - t0) * 13 * n;
+#pragma unroll
+        for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+#pragma unroll
+        for (int r = 0; r < 13; ++r) s[r] = nxt[r];
+        if (t > t0) {
+            const float* tp = tape + (long long)(t - 1 - t0) * 13 * n;
+#pragma unroll
+            for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
+        }
+        step_core<NR, false, false, true>(s, C, P, gt, a.dt, a.g, nullptr, nullptr, &A);
+    }
+}
+
+// Block = 64 vehicles x 2 wavefronts (see the file comment).  Every thread
+// passes the same barriers: no early exit, lanes past n only skip the work.
+template <int NR>
+__global__ __launch_bounds__(128) void k_rollout_adj(RolloutArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
     int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
     __shared__ int sh[2];
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const float* gt = rollout_stage(a, lds, loff, sh, i);
-    if (i >= a.n) return;
-    const long long ld = a.ld, n = a.n;
-    Params P;
-    load_params<true>(P, gt, a.vparams, ld, i);
-    Cmd C;
-    derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
+    const bool reverse_wave = threadIdx.x < 64;       // uniform per wavefront
+    const long long base = (long long)blockIdx.x * 64;
+    const long long i = base + (threadIdx.x & 63);
+    const float* gt = rollout_stage(a, lds, loff, sh, base, base + 64 < a.n ? base + 64 : a.n, i);
+    const bool act = i < a.n;
+    const long long ld = a.ld;
+    const long long buf = (long long)a.m * 13 * a.n;   // floats per tape buffer
+    Params P = {};
+    Cmd C = {};
+    if (act) {
+        load_params<true>(P, gt, a.vparams, ld, i);
+        derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
+    }
+    const int last = a.n_ckpt - 1;
+    if (!reverse_wave && act) recompute_segment<NR>(a, P, C, gt, last, a.tape + (last & 1) * buf, i);
+    __syncthreads();
     Adj A;
 #pragma unroll
     for (int r = 0; r < 13; ++r) A.lam[r] = 0.0f;
@@ -108,43 +167,21 @@ __global__ __launch_bounds__(256) void k_rollout_adj(RolloutArgs a) {
     for (int r = 0; r < 10; ++r) A.gb[r] = 0.0f;
     A.gx = C.t0; A.gy = C.t1; A.gz = C.t2;
     A.w_omega = a.w_omega;
-    float s[13];
-    for (int seg = a.n_ckpt - 1; seg >= 0; --seg) {
-        const int t0 = seg * a.m;
-        const int t1 = t0 + a.m < a.T ? t0 + a.m : a.T;
-        const float* ck = a.ckpt + (long long)seg * 13 * n;
-#pragma unroll
-        for (int r = 0; r < 13; ++r) s[r] = ck[r * n + i];
-        for (int t = t0; t < t1; ++t) {
-            float* tp = a.tape + (long long)(t - t0) * 13 * n;
-#pragma unroll
-            for (int r = 0; r < 13; ++r) tp[r * n + i] = s[r];
-            if (t + 1 < t1) step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+    for (int seg = last; seg >= 0; --seg) {
+        if (reverse_wave) {
+            if (act) reverse_segment<NR>(a, P, C, gt, seg, a.tape + (seg & 1) * buf, i, A);
+        } else if (seg > 0 && act) {
+            recompute_segment<NR>(a, P, C, gt, seg - 1, a.tape + ((seg - 1) & 1) * buf, i);
         }
-        // reverse sweep; the next (earlier) tape entry is loaded while the
-        // current step's reverse runs, hiding the load latency
-        float nxt[13];
-        {
-            const float* tp = a.tape + (long long)(t1 - 1 - t0) * 13 * n;
-#pragma unroll
-            for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
-        }
-        for (int t = t1 - 1; t >= t0; --t) {
-#pragma unroll
-            for (int r = 0; r < 13; ++r) s[r] = nxt[r];
-            if (t > t0) {
-                const float* tp = a.tape + (long long)(t - 1 - t0) * 13 * n;
-#pragma unroll
-                for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
-            }
-            step_core<NR, false, false, true>(s, C, P, gt, a.dt, a.g, nullptr, nullptr, &A);
-        }
+        __syncthreads();
     }
-    const float sc = a.seed_grad;
+    if (reverse_wave && act) {
+        const float sc = a.seed_grad;
 #pragma unroll
-    for (int r = 0; r < 10; ++r) a.dgains[r * ld + i] = A.gb[r] * sc;
+        for (int r = 0; r < 10; ++r) a.dgains[r * ld + i] = A.gb[r] * sc;
 #pragma unroll
-    for (int r = 0; r < 13; ++r) a.dx0[r * ld + i] = A.lam[r] * sc;
+        for (int r = 0; r < 13; ++r) a.dx0[r * ld + i] = A.lam[r] * sc;
+    }
 }
 
 const void* rollout_fwd_kernel(int nr_class) {
