@@ -6,8 +6,9 @@ Workload (default): 1,048,576 X-quads, command mode drawn per vehicle from
 every vehicle (controller, allocation, clamping, integration).  The timed
 region runs K steps with the autotuned fused policy (k steps per launch,
 state in registers, replayed from a HIP graph); the same K steps are also
-timed as K plain per-step launches.  Inputs are resident in HBM before
-timing starts.  Prints one JSON line.
+timed as K plain per-step launches (no graph) and as K host calls of
+ag_step(1).  Inputs are resident in HBM before timing starts.  Prints one
+JSON line.
 """
 import argparse
 import json
@@ -212,7 +213,7 @@ def bench_per_step_large(sync, steps=200):
         sim.set_exec(kind=0, block=blk, use_graph=0)
         sim.raw_step(10)
         sync()
-        t = event_time(sim.stream, lambda: [sim.raw_step(1) for _ in range(steps)])
+        t = event_time(sim.stream, lambda: sim.raw_step(steps))
         if best is None or t < best[0]:
             best = (t, blk)
     sim.close()
@@ -321,6 +322,8 @@ def main():
         t_evt["fused"] = event_time(sim.stream, lambda: sim.raw_step(K))
 
     t_fused = timed(run_fused, sync)
+    # the same K steps timed four more times (spread of the measurement)
+    repeats = [timed(lambda: sim.raw_step(K), sync) for _ in range(4)]
     launches = math.ceil(K / k)
     kern_fused = t_evt["fused"] / launches
     value = wl.n * K / t_fused
@@ -328,13 +331,18 @@ def main():
         f"kernel avg {kern_fused * 1e6:.1f} us over {launches} launches")
 
     # ---- plain per-step launches ----------------------------------------------
+    # K kernel launches without a graph, issued by the library's own launch
+    # loop (ag_step(K) under the per-step policy); the same K steps as K host
+    # calls of ag_step(1) are timed as well, where the host's per-call time
+    # can leave the GPU idle between launches.
     per_step = None
     if not args.no_per_step:
         best = None
         for blk in ((args.per_step_block,) if args.per_step_block else (64, 128, 256, 512)):
             sim.set_exec(kind=0, block=blk, use_graph=0)
             sim.raw_step(20)
-            t = timed(lambda: sim.raw_step(50), sync)
+            sync()
+            t = event_time(sim.stream, lambda: sim.raw_step(100)) / 100
             if best is None or t < best[0]:
                 best = (t, blk)
         sim.set_exec(kind=0, block=best[1], use_graph=0)
@@ -342,25 +350,29 @@ def main():
         sync()
 
         def run_plain():
+            t_evt["plain"] = event_time(sim.stream, lambda: sim.raw_step(K))
+
+        t_plain = timed(run_plain, sync)
+        kern_plain = t_evt["plain"] / K
+
+        def run_calls():
             for _ in range(K):
                 sim.raw_step(1)
 
-        def run_plain_evt():
-            t_evt["plain"] = event_time(sim.stream, run_plain)
-
-        t_plain = timed(run_plain_evt, sync)
-        kern_plain = t_evt["plain"] / K
+        t_calls = timed(run_calls, sync)
         gbs = BYTES_PER_VSTEP * wl.n / kern_plain / 1e9
         per_step = {
             "value": wl.n * K / t_plain, "ms_per_step": t_plain / K * 1e3, "block": best[1],
             "kernel_avg_us": kern_plain * 1e6,
+            "host_calls": {"value": wl.n * K / t_calls, "ms_per_step": t_calls / K * 1e3,
+                           "what": "K host calls of ag_step(1)"},
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS,
                          "traffic": COUNTERS["per_step_bytes"] if counters_valid() else None,
                          "algorithmic_bytes": BYTES_PER_VSTEP * wl.n},
         }
         log(f"per-step: {t_plain * 1e3:.2f} ms -> {per_step['value']:.3e} vehicle-steps/s, "
-            f"kernel {kern_plain * 1e6:.1f} us = {gbs:.0f} GB/s")
+            f"kernel {kern_plain * 1e6:.1f} us = {gbs:.0f} GB/s; as host calls {t_calls * 1e3:.2f} ms")
 
     # achieved = algorithmic flops of the timed launches / their event time
     # (the last launch of a K that k does not divide runs fewer steps)
@@ -374,6 +386,7 @@ def main():
         "steps": K,
         "warmup": W,
         "ms_per_step": t_fused / K * 1e3,
+        "repeat_ms_per_step": [t / K * 1e3 for t in repeats],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -427,9 +440,10 @@ def main():
                                    "dispatches": 3}
     if not args.no_extras:
         fma = probe.valu_fma_peak()
-        cbw = probe.copy_bandwidth()
+        cbw, by_grid = probe.copy_bandwidth()
         out["measured_peaks"] = {"fp32_fma_lane_ops_per_s": fma, "fp32_fma_tflops": 2 * fma / 1e12,
-                                 "copy_GBs": cbw / 1e9}
+                                 "copy_GBs": cbw / 1e9,
+                                 "copy_GBs_by_grid": {str(g): r / 1e9 for g, r in by_grid.items()}}
         out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / (2 * fma / 1e12)
         if valid:
             # VALU issue rate against the rate a pure-FMA probe kernel reaches

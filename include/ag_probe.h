@@ -9,7 +9,8 @@
  * agp_copy: plain vectorised device copy of `bytes` bytes (multiple of 16)
  *   from src to dst (device pointers, 16-byte aligned): reads and writes
  *   exactly `bytes` each; used to calibrate the HBM byte counters and to
- *   measure the achievable copy bandwidth.
+ *   measure the achievable copy bandwidth.  `blocks` x 256 lanes walk the
+ *   16-byte elements grid-stride; blocks = 0 launches one lane per element.
  * Both enqueue on `stream` (hipStream_t) and return 0, or a hipError_t code.
  */
 #ifndef AG_PROBE_H
@@ -20,7 +21,7 @@
 extern "C" {
 #endif
 int agp_valu_fma(void* stream, float* out, int32_t blocks, int32_t iters);
-int agp_copy(void* stream, void* dst, const void* src, size_t bytes);
+int agp_copy(void* stream, void* dst, const void* src, size_t bytes, int32_t blocks);
 #ifdef __cplusplus
 }
 #endif

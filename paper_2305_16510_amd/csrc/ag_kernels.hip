@@ -119,10 +119,9 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
     for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const long long base = tile * TILE;
         const long long end = base + TILE < a.n ? base + TILE : a.n;
-        stage_groups(lds, loff, sh, a.gtab, a.goff, a.n_groups, base, end);
-        const int cnt = sh[1];
-
         float s[VPL][13];
+        float tg[VPL][4];
+        int md[VPL];
         Cmd C[VPL];
         Params P[VPL];
         const float* gt[VPL];
@@ -130,6 +129,8 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
         bool act[VPL];
         int sat_last[VPL];
         bool did_reset[VPL];
+        // the tile's state and command loads are issued before the group-table
+        // staging and its barriers, so that their latencies overlap
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             const long long i = base + (long long)v * B + threadIdx.x;
@@ -140,10 +141,20 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
             if (act[v]) {
 #pragma unroll
                 for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + i];
+                md[v] = (int)a.mode[i];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + i];
+            }
+        }
+        stage_groups(lds, loff, sh, a.gtab, a.goff, a.n_groups, base, end);
+        const int cnt = sh[1];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+            if (act[v]) {
+                const long long i = idx[v];
                 gt[v] = lane_group(lds, loff, cnt, i);
                 load_params<VP>(P[v], gt[v], a.vparams, ld, i);
-                derive_cmd(C[v], (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i],
-                           a.target[3 * ld + i]);
+                derive_cmd(C[v], md[v], tg[v][0], tg[v][1], tg[v][2], tg[v][3]);
                 if constexpr (TRK) derive_traj(C[v], a.traj, ld, i);
             }
         }

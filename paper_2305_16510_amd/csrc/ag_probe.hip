@@ -18,6 +18,7 @@ __global__ __launch_bounds__(256) void k_valu_fma(float* out, int iters) {
     out[blockIdx.x * 256 + threadIdx.x] = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
 }
 
+// Plain copy, one 16-byte element per lane and grid-stride step.
 __global__ __launch_bounds__(256) void k_copy(float4* __restrict__ dst, const float4* __restrict__ src, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
 }
@@ -30,10 +31,15 @@ extern "C" int agp_valu_fma(void* stream, float* out, int32_t blocks, int32_t it
     return (int)hipGetLastError();
 }
 
-extern "C" int agp_copy(void* stream, void* dst, const void* src, size_t bytes) {
-    if (!dst || !src || bytes % 16) return (int)hipErrorInvalidValue;
+extern "C" int agp_copy(void* stream, void* dst, const void* src, size_t bytes, int32_t blocks_in) {
+    if (!dst || !src || bytes % 16 || blocks_in < 0) return (int)hipErrorInvalidValue;
     const size_t n = bytes / 16;
-    const unsigned blocks = 256 * 8;
+    const size_t one_each = (n + 255) / 256;          // blocks for one element per lane
+    size_t nb = blocks_in > 0 ? (size_t)blocks_in : one_each;
+    if (nb > one_each) nb = one_each;
+    if (nb < 1) nb = 1;
+    if (nb > 0x7fffffffu) return (int)hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)nb;
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (float4*)dst, (const float4*)src, n);
     return (int)hipGetLastError();
 }

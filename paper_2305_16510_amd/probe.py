@@ -15,7 +15,7 @@ def load():
             raise RuntimeError(f"probe library not built: {PATH}")
         _lib = C.CDLL(PATH)
         _lib.agp_valu_fma.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]
-        _lib.agp_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]
+        _lib.agp_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]
     return _lib
 
 
@@ -43,17 +43,22 @@ def valu_fma_peak(blocks=4096, iters=4096):
     return blocks * 256 * iters * 8 / t
 
 
-def copy_bandwidth(nbytes=1 << 30):
-    """Measured device copy bandwidth (bytes read + written per second)."""
+def copy_bandwidth(nbytes=1 << 30, grids=(0, 2048, 8192, 32768)):
+    """Measured device copy bandwidth (bytes read + written per second): the
+    best of plain copies with one lane per 16-byte element (grid 0) and
+    grid-stride copies of the given block counts; also returns the rate of
+    each grid."""
     L = load()
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     s = torch.cuda.current_stream()
-    run = lambda: L.agp_copy(C.c_void_p(s.cuda_stream), C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
-                             nbytes)
-    run()
-    t = _time(s, run)
-    return 2 * nbytes / t
+    rates = {}
+    for g in grids:
+        run = lambda: L.agp_copy(C.c_void_p(s.cuda_stream), C.c_void_p(dst.data_ptr()),
+                                 C.c_void_p(src.data_ptr()), nbytes, g)
+        run()
+        rates[g] = 2 * nbytes / _time(s, run)
+    return max(rates.values()), rates
 
 
 def copy_once(nbytes):
@@ -63,5 +68,5 @@ def copy_once(nbytes):
     dst = torch.empty_like(src)
     s = torch.cuda.current_stream()
     for _ in range(3):
-        L.agp_copy(C.c_void_p(s.cuda_stream), C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes)
+        L.agp_copy(C.c_void_p(s.cuda_stream), C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, 2048)
     torch.cuda.synchronize()
