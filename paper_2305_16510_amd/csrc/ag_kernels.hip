@@ -6,7 +6,8 @@
 // block stages the table entries of the vehicle groups its tile overlaps in
 // LDS (rotor allocation matrix and pseudo-inverse, inverses of mass and
 // inertia, default gains); lanes find their group by scanning the staged
-// group offsets.
+// group offsets.  A per-step launch of a single group loads its one entry
+// ahead of the state, so the staging waits for the entry alone.
 //
 // k_step<NR, VP, RESET, VPL, ONE, OBS, TRK> is both the per-step kernel (ONE: one step
 // per launch, one tile per block) and the fused kernel (k steps per launch
@@ -96,16 +97,13 @@ __device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, l
     }
 }
 
-template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS, bool TRK>
-__global__ __launch_bounds__(512) void k_step(StepArgs a) {
-    extern __shared__ float4 lds4[];
-    float* lds = reinterpret_cast<float*>(lds4);
-    int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
-    __shared__ int sh[2];
-
+// The tiles of one block.  UNI (per-step kernels of a single-group launch):
+// the one group entry is loaded ahead of the state and written to LDS
+// without the group search and its extra barrier.
+template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS, bool TRK, bool UNI>
+__device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* loff, int* sh) {
     const int B = blockDim.x;
     const long long TILE = (long long)B * VPL;
-    const long long ntiles = (a.n + TILE - 1) / TILE;
     const long long tbase = a.d_step ? (*a.d_step + a.t_off) : a.t0;
     const int K = ONE ? 1 : a.k;
     const long long ld = a.ld;
@@ -116,8 +114,7 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
     long long c_sat = 0, c_res = 0, c_nonf = 0, c_fin = 0, c_pos = 0;
     double s_err = 0.0, s_w = 0.0;
 
-    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long long base = tile * TILE;
+    auto tile_body = [&](const long long base) {
         const long long end = base + TILE < a.n ? base + TILE : a.n;
         float s[VPL][13];
         float tg[VPL][4];
@@ -129,8 +126,22 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
         bool act[VPL];
         int sat_last[VPL];
         bool did_reset[VPL];
+        // Single group: the entry's loads go first, so the LDS write below
+        // waits for them alone (loads complete in order), not for the state.
+        // (Indices are clamped into range instead of branching, so that all
+        // these loads sit in one basic block and each wait is exact.)
+        // Lanes past the entry's end read and later write its last float, so
+        // duplicate LDS writes carry identical values.
+        const int e0 = (int)threadIdx.x < GSTRIDE ? (int)threadIdx.x : GSTRIDE - 1;
+        const int e1 = (int)threadIdx.x + B < GSTRIDE ? (int)threadIdx.x + B : GSTRIDE - 1;
+        float te0 = 0.0f, te1 = 0.0f;
+        if constexpr (UNI) {
+            te0 = a.gtab[e0];
+            te1 = a.gtab[e1];
+        }
         // the tile's state and command loads are issued before the group-table
-        // staging and its barriers, so that their latencies overlap
+        // staging and its barriers, so that their latencies overlap; lanes past
+        // n load vehicle n - 1 and discard it
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             const long long i = base + (long long)v * B + threadIdx.x;
@@ -138,21 +149,27 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
             act[v] = i < a.n;
             sat_last[v] = 0;
             did_reset[v] = false;
-            if (act[v]) {
+            const long long il = act[v] ? i : a.n - 1;
 #pragma unroll
-                for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + i];
-                md[v] = (int)a.mode[i];
+            for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + il];
+            md[v] = (int)a.mode[il];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + i];
-            }
+            for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + il];
         }
-        stage_groups(lds, loff, sh, a.gtab, a.goff, a.n_groups, base, end);
-        const int cnt = sh[1];
+        int cnt = 1;
+        if constexpr (UNI) {
+            lds[e0] = te0;
+            lds[e1] = te1;
+            __syncthreads();
+        } else {
+            stage_groups(lds, loff, sh, a.gtab, a.goff, a.n_groups, base, end);
+            cnt = sh[1];
+        }
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             if (act[v]) {
                 const long long i = idx[v];
-                gt[v] = lane_group(lds, loff, cnt, i);
+                gt[v] = UNI ? lds : lane_group(lds, loff, cnt, i);
                 load_params<VP>(P[v], gt[v], a.vparams, ld, i);
                 derive_cmd(C[v], md[v], tg[v][0], tg[v][1], tg[v][2], tg[v][3]);
                 if constexpr (TRK) derive_traj(C[v], a.traj, ld, i);
@@ -257,10 +274,34 @@ __global__ __launch_bounds__(512) void k_step(StepArgs a) {
             }
         }
         __syncthreads();   // LDS is restaged for the next tile
+    };
+    if constexpr (ONE) {
+        // a per-step launch has one block per tile (its grid is the tile count),
+        // and no loop: nothing written by the block precedes its table reads
+        const long long base = (long long)blockIdx.x * TILE;
+        if (base < a.n) tile_body(base);
+    } else {
+        const long long ntiles = (a.n + TILE - 1) / TILE;
+        for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile * TILE);
     }
     if constexpr (OBS) {
         if (a.slots) block_stats(a.slots, c_sat, c_res, c_nonf, c_fin, c_pos, s_err, s_w);
     }
+}
+
+template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS, bool TRK>
+__global__ __launch_bounds__(512) void k_step(StepArgs a) {
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
+    __shared__ int sh[2];
+    if constexpr (ONE) {
+        if (a.n_groups == 1) {     // uniform across the grid
+            step_tiles<NR, VP, RESET, VPL, ONE, OBS, TRK, true>(a, lds, loff, sh);
+            return;
+        }
+    }
+    step_tiles<NR, VP, RESET, VPL, ONE, OBS, TRK, false>(a, lds, loff, sh);
 }
 
 // ---- statistics fold: slots -> cumulative accumulator (one block) ---------
