@@ -382,6 +382,10 @@ def main():
     # (the last launch of a K that k does not divide runs fewer steps)
     tflops = FLOPS_PER_VSTEP * wl.n * K / t_evt["fused"] / 1e12
     valid = counters_valid()
+    # VALU utilisation: lane-instructions issued per second against the chip's
+    # peak issue rate (157.3 TFLOP/s = 78.6e12 single-lane FMAs per second)
+    valu_util = (COUNTERS["fused_valu_per_vstep"] * wl.n * K / t_evt["fused"]) / (FP32_PEAK_TFLOPS * 1e12 / 2) \
+        if valid else None
     out = {
         "metric": "vehicle-steps/s at 1M quads (fused vs per-step), %HBM/VALU peak; adjoint s/step",
         "value": value,
@@ -405,6 +409,7 @@ def main():
                      "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
                      "steps_per_launch": k, "flops_per_vehicle_step": FLOPS_PER_VSTEP,
                      "valu_instr_per_vehicle_step": COUNTERS["fused_valu_per_vstep"] if valid else None,
+                     "valu_issue_frac_of_peak": valu_util,
                      "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},
         "per_step": per_step,
         "fused_over_per_step": (value / per_step["value"]) if per_step else None,

@@ -371,16 +371,19 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     float raws[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
+        raws[r] = 0.0f;
+        if constexpr (WANT_U) u_out[r] = 0.0f;
+        // in a mixed launch, lanes with fewer rotors skip slots 4..7 (every
+        // layout has at least 4); a wavefront inside one group skips them
+        // entirely, and a skipped slot leaves the sums as a zero thrust would
+        if (MIXED && r >= 4 && r >= P.nr) continue;
         const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
         const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
         const float raw = ap.x * f + ap.y * a1 + ap.z * a2 + ap.w * M2;
         raws[r] = raw;
-        // clamp to [u_min, u_max] as one median-of-three; in a mixed launch the
-        // slots beyond the group's rotor count are masked to zero
-        const bool act = MIXED ? r < P.nr : true;
-        float u = __builtin_amdgcn_fmed3f(raw, P.umin, P.umax);
-        if constexpr (MIXED) u = act ? u : 0.0f;
-        nsat += (int)(act & ((raw < P.umin) | (raw > P.umax)));
+        // clamp to [u_min, u_max] as one median-of-three
+        const float u = __builtin_amdgcn_fmed3f(raw, P.umin, P.umax);
+        nsat += (int)((raw < P.umin) | (raw > P.umax));
         if (r == 0) {
             fa = u * ac.x;
             S0 = u * ac.y;
