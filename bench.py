@@ -423,16 +423,16 @@ def main():
 
     if not args.no_extras:
         wp = workloads.paper_context()
-        sp = Sim.from_workload(wp)
-        sp.set_exec(**{kk: tuned[kk] for kk in ("kind", "block", "vpl", "k", "grid", "use_graph")})
+        sp = Sim.from_workload(wp, autotune_scratch=True)
+        tuned_p = sp.autotune(args.probe_steps)
         sp.prepare(K)
         sp.raw_step(K)
         sync()
         tp = timed(lambda: sp.raw_step(K), sync)
-        out["paper_shape"] = {"value": wp.n * K / tp, "n_vehicles": wp.n,
+        out["paper_shape"] = {"value": wp.n * K / tp, "n_vehicles": wp.n, "exec": tuned_p,
                               "workload": "2^17 quads, constant attitude or velocity commands, dt=0.01"}
         sp.close()
-        log(f"paper shape 2^17: {wp.n * K / tp:.3e} vehicle-steps/s")
+        log(f"paper shape 2^17: {wp.n * K / tp:.3e} vehicle-steps/s ({tuned_p})")
         out["adjoint"] = bench_adjoint(sync)
         out["uneven_groups"] = bench_uneven(sync)
         out["large_resets"] = bench_large(sync)
