@@ -158,7 +158,9 @@ ag_status ag_workspace_size(const ag_config* cfg, size_t* bytes);
  * from ag_workspace_size, 256-byte aligned).  Enqueues on cfg->stream. */
 ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_bytes, ag_handle* out);
 
-/* Release the host-side handle and its graphs (device buffers stay with the caller). */
+/* Wait for the handle's stream, then release the host-side handle and its
+ * graphs (device buffers stay with the caller).  The handle is freed even
+ * when the wait reports a device error (returned as AG_E_HIP). */
 ag_status ag_destroy(ag_handle h);
 
 /* New commands for vehicles [first, first+count): copies mode_src[i] and

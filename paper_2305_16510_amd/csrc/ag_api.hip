@@ -505,9 +505,12 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
 
 ag_status ag_destroy(ag_handle h) {
     if (!h) return AG_E_INVALID;
+    // let launches and graph replays still queued on the stream finish before
+    // their executable graphs are destroyed
+    const hipError_t e = hipStreamSynchronize(h->stream);
     drop_graphs(h);
     delete h;
-    return AG_OK;
+    return e == hipSuccess ? AG_OK : AG_E_HIP;
 }
 
 ag_status ag_set_targets(ag_handle h, int64_t first, int64_t count, const int8_t* mode_src,

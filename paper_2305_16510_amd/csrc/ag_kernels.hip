@@ -200,7 +200,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                     if (mask_hit(mw[v], tbase + st, a.thr)) {
                         float gx, gy, gz;
                         redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
-                        if (C[v].mode == 0) derive_cmd(C[v], 0, gx, gy, gz, 0.0f);
+                        if (C[v].mode == 0) set_position_goal(C[v], gx, gy, gz);
                         if (a.goal) {
                             a.goal[idx[v]] = gx;
                             a.goal[ld + idx[v]] = gy;

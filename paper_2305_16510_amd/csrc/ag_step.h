@@ -155,6 +155,14 @@ AG_DEV void derive_cmd(Cmd& C, int mode, float t0, float t1, float t2, float t3)
     sincosf(b, &C.sb, &C.cb);
 }
 
+// Position-mode command to goal (gx, gy, gz) with psi_d = 0: the same fields
+// as derive_cmd(C, 0, gx, gy, gz, 0) (sin 0 = 0 and cos 0 = 1 exactly).
+AG_DEV void set_position_goal(Cmd& C, float gx, float gy, float gz) {
+    C.mode = 0;
+    C.t0 = gx; C.t1 = gy; C.t2 = gz; C.t3 = 0.0f;
+    C.sa = 0.0f; C.ca = 1.0f; C.sb = 0.0f; C.cb = 1.0f;
+}
+
 // Trajectory rows of vehicle i (x_d, v_d, a_d, psi_d, Omega_d, dOmega_d).
 AG_DEV void derive_traj(Cmd& C, const float* __restrict__ tr, int64_t ld, int64_t i) {
     C.xd0 = tr[i]; C.xd1 = tr[ld + i]; C.xd2 = tr[2 * ld + i];
