@@ -128,7 +128,10 @@ typedef struct {
  * state in registers for k steps per launch, vpl vehicles per lane, a grid-
  * stride loop over tiles of block*vpl vehicles (grid 0 = one block per tile),
  * replayed from a cached HIP graph when use_graph is 1 and the stream is not
- * null.  Every policy gives bitwise identical states. */
+ * null.  Every policy gives bitwise identical states.  With automatic resets
+ * a fused launch first finds, lists and redraws the resets of its k steps
+ * (k <= 64 then) in dense kernels, holding up to one event per vehicle in
+ * the workspace; events beyond that are redrawn in the step loop. */
 typedef struct {
     int32_t kind, block, vpl, k, grid, use_graph;
 } ag_exec;

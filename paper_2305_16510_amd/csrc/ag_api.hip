@@ -28,7 +28,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
     size_t gtab, goff, d_step, acc, slots, block_counts, mask, scratch, total;
-    long long nslots, nblocks;
+    size_t ev_bits, ev_off, ev_bc, ev_total, ev_list, ev_data;
+    long long nslots, nblocks, ev_cap;
 };
 
 WsLayout ws_layout(const ag_config* c) {
@@ -45,6 +46,17 @@ WsLayout ws_layout(const ag_config* c) {
     L.mask = off; off = align_up(off + (size_t)c->n);
     L.scratch = off;
     if (c->autotune_scratch) off = align_up(off + (size_t)(AG_STATE_DIM + AG_TARGET_DIM) * c->ld * sizeof(float));
+    // reset events of fused launches (automatic resets): room for n events per
+    // launch, i.e. one per vehicle; further events are redrawn in the step loop
+    L.ev_cap = (c->auto_reset && c->reset_prob > 0.0f) ? c->n : 0;
+    if (L.ev_cap > 0) {
+        L.ev_bits = off; off = align_up(off + (size_t)c->n * sizeof(unsigned long long));
+        L.ev_off = off; off = align_up(off + (size_t)c->n * sizeof(int32_t));
+        L.ev_bc = off; off = align_up(off + (size_t)L.nblocks * sizeof(long long));
+        L.ev_total = off; off = align_up(off + sizeof(long long));
+        L.ev_list = off; off = align_up(off + (size_t)L.ev_cap * sizeof(long long));
+        L.ev_data = off; off = align_up(off + (size_t)16 * L.ev_cap * sizeof(float));
+    }
     L.total = off;
     return L;
 }
@@ -96,6 +108,7 @@ struct ag_sim {
     std::string err;
     int num_cus;
     std::vector<std::pair<long long, int>> span_cache;
+    EvBufs ev;
 };
 
 namespace {
@@ -265,11 +278,31 @@ StepArgs base_args(ag_handle h) {
         a.lo[k] = h->cfg.reset_lo[k];
         a.hi[k] = h->cfg.reset_hi[k];
     }
+    a.ev = h->ev;
     return a;
+}
+
+// Whether fused launches of the current handle take their resets from the
+// event kernels.
+bool uses_events(ag_handle h, const ag_exec& e) { return h->reset_on && e.kind == 1 && h->ev.cap > 0; }
+
+// The event kernels of one launch, in order (they take the launch's arguments).
+struct EvKernels {
+    const void* fn[4];
+    dim3 grid[4], block[4];
+};
+
+EvKernels event_kernels(ag_handle h) {
+    const unsigned nb = (unsigned)h->L.nblocks;
+    const unsigned nr = (unsigned)((h->ev.cap + 255) / 256);
+    return EvKernels{{ev_mask_kernel(), ev_scan_kernel(), ev_scatter_kernel(), ev_redraw_kernel()},
+                     {dim3(nb), dim3(1), dim3(nb), dim3(nr)},
+                     {dim3(kResetBlock), dim3(1024), dim3(kResetBlock), dim3(256)}};
 }
 
 struct LaunchShape {
     const void* fn;
+    const void* fn_fb;   // fused launches with resets: the variant for overfull event buffers, run after fn
     dim3 grid, block;
     size_t shmem;
     int span;
@@ -290,10 +323,13 @@ std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
     long long grid = (one || e.grid == 0) ? ntiles : std::min<long long>(e.grid, ntiles);
     if (grid > h->L.nslots) grid = h->L.nslots;
     if (grid > 2147483647LL) return "grid too large";
+    if (h->reset_on && !one && e.k > 64) return "with automatic resets exec.k must be <= 64";
     const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
     const bool trk = h->cfg.traj != nullptr;
     if (trk && vpl != 1) return "with a trajectory buffer exec.vpl must be 1";
-    s.fn = step_kernel(h->nr_class, h->vp, h->reset_on, vpl, one, obs, trk);
+    const bool events = h->reset_on && !one && h->ev.cap > 0;
+    s.fn = step_kernel(h->nr_class, h->vp, events ? 2 : (h->reset_on ? 1 : 0), vpl, one, obs, trk);
+    s.fn_fb = events ? step_kernel(h->nr_class, h->vp, 1, vpl, one, obs, trk) : nullptr;
     s.grid = dim3((unsigned)grid);
     s.block = dim3((unsigned)e.block);
     s.span = span;
@@ -324,7 +360,15 @@ ag_status run_direct(ag_handle h, const ag_exec& e, int n_steps, StepArgs a, boo
         a.t0 = h->t + done;
         a.k = std::min(k, n_steps - done);
         a.flags_accumulate = done > 0;
+        if (uses_events(h, e)) {
+            const EvKernels ek = event_kernels(h);
+            for (int q = 0; q < 4; ++q) {
+                ag_status st = launch(h, ek.fn[q], ek.grid[q], ek.block[q], 0, &a);
+                if (st != AG_OK) return st;
+            }
+        }
         ag_status st = launch(h, s.fn, s.grid, s.block, s.shmem, &a);
+        if (st == AG_OK && s.fn_fb) st = launch(h, s.fn_fb, s.grid, s.block, s.shmem, &a);
         if (st != AG_OK) return st;
     }
     if (fold && a.slots) return launch_fold(h, (int)s.grid.x, n_steps);
@@ -360,9 +404,22 @@ ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
         a.t_off = done;
         a.k = std::min(k, n_steps - done);
         a.flags_accumulate = done > 0;
+        if (uses_events(h, h->exec)) {
+            const EvKernels ek = event_kernels(h);
+            for (int q = 0; q < 4; ++q) {
+                ag_status st = add_node(h, g, &node, prev ? &prev : nullptr, ek.fn[q], ek.grid[q], ek.block[q], 0, &a);
+                if (st != AG_OK) { hipGraphDestroy(g); return st; }
+                prev = node;
+            }
+        }
         ag_status st = add_node(h, g, &node, prev ? &prev : nullptr, s.fn, s.grid, s.block, s.shmem, &a);
         if (st != AG_OK) { hipGraphDestroy(g); return st; }
         prev = node;
+        if (s.fn_fb) {
+            st = add_node(h, g, &node, &prev, s.fn_fb, s.grid, s.block, s.shmem, &a);
+            if (st != AG_OK) { hipGraphDestroy(g); return st; }
+            prev = node;
+        }
     }
     if (a.slots) {
         FoldArgs f{h->slots, (int)s.grid.x, h->acc, n_steps, 1};
@@ -443,6 +500,16 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
     h->block_counts = reinterpret_cast<int32_t*>(h->ws + L.block_counts);
     h->mask_buf = reinterpret_cast<uint8_t*>(h->ws + L.mask);
     h->scratch = cfg->autotune_scratch ? reinterpret_cast<float*>(h->ws + L.scratch) : nullptr;
+    h->ev = EvBufs{};
+    if (L.ev_cap > 0) {
+        h->ev.bits = reinterpret_cast<unsigned long long*>(h->ws + L.ev_bits);
+        h->ev.off = reinterpret_cast<int32_t*>(h->ws + L.ev_off);
+        h->ev.block_counts = reinterpret_cast<long long*>(h->ws + L.ev_bc);
+        h->ev.total = reinterpret_cast<long long*>(h->ws + L.ev_total);
+        h->ev.list = reinterpret_cast<long long*>(h->ws + L.ev_list);
+        h->ev.data = reinterpret_cast<float*>(h->ws + L.ev_data);
+        h->ev.cap = L.ev_cap;
+    }
     int maxr = 4;
     for (auto& g : h->groups) maxr = std::max(maxr, g.n_rotors);
     bool uniform = true;
@@ -625,6 +692,7 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     a.wrench_out = nullptr;
     a.rotor_out = nullptr;
     a.flags_out = nullptr;
+    a.goal = nullptr;          // trials on scratch copies leave the caller's goals alone
     hipEvent_t e0, e1;
     AG_HIP(h, hipEventCreate(&e0));
     AG_HIP(h, hipEventCreate(&e1));

@@ -26,6 +26,22 @@ struct StatAcc {
     double pos_err_sum, omega_sum;
 };
 
+// Reset events of one fused launch (steps tb .. tb + k - 1, k <= 64), found
+// and redrawn before the launch by dense kernels, so that the step loop only
+// copies a redrawn state: bits[i] has bit j set when vehicle i resets before
+// step tb + j; off[i] is the index of its first event in vehicle-major order;
+// list[e] = (i << 6) | j; data is [16][cap] (13 state rows, 3 goal rows).
+// Events with index >= cap are redrawn in the step loop itself.
+struct EvBufs {
+    unsigned long long* bits;  // [n]
+    int32_t* off;              // [n]
+    long long* block_counts;   // [nblocks of 256 vehicles] (counts, then exclusive offsets)
+    long long* total;          // [1]
+    long long* list;           // [cap]
+    float* data;               // [16][cap]
+    long long cap;
+};
+
 struct StepArgs {
     float* state;              // [13][ld] (read and written in place)
     const int8_t* mode;        // [ld]
@@ -52,6 +68,7 @@ struct StepArgs {
     unsigned long long thr;    // reset threshold (word < thr)
     uint32_t index_base;
     float lo[3], hi[3];
+    EvBufs ev;                 // reset events (RESET kernels)
 };
 
 struct ResetArgs {
@@ -92,8 +109,12 @@ struct RolloutArgs {
 constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
 
 // Kernel lookup (defined in ag_kernels.hip).  nr_class: 4, 6 or 8 rotors in
-// every group, or 0 for a launch mixing rotor counts.
-const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs, bool trk);
+// every group, or 0 for a launch mixing rotor counts.  rst: 0 no resets; 1
+// resets (a fused launch takes them from the event kernels and redraws events
+// past the buffer itself); 2 fused launch whose events all fit the buffer.
+// A fused launch with resets runs the rst = 2 and rst = 1 kernels in turn;
+// each leaves at once unless the launch's event count selects it.
+const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk);
 const void* fold_kernel();
 const void* advance_kernel();
 const void* set_step_kernel();
@@ -197,5 +218,13 @@ struct TaskArgs {
 
 const void* actions_kernel();
 const void* observe_kernel();
+
+// Reset events of a fused launch: mask (bits and per-block counts), scan,
+// scatter (per-vehicle offsets and the event list), redraw (one lane per
+// event).  They take the launch's StepArgs (steps, keys, threshold, bounds, ev).
+const void* ev_mask_kernel();
+const void* ev_scan_kernel();
+const void* ev_scatter_kernel();
+const void* ev_redraw_kernel();
 
 }  // namespace ag

@@ -9,13 +9,15 @@
 // group offsets.  A per-step launch of a single group loads its one entry
 // ahead of the state, so the staging waits for the entry alone.
 //
-// k_step<NR, VP, RESET, VPL, ONE, OBS, TRK> is both the per-step kernel (ONE: one step
+// k_step<NR, VP, RST, VPL, ONE, OBS, TRK> is both the per-step kernel (ONE: one step
 // per launch, one tile per block) and the fused kernel (k steps per launch
 // with the state held in registers, VPL vehicles per lane, grid-stride loop
 // over tiles).  A grid that is a multiple of 8 keeps each tile on the same
 // XCD (and so the same L2) from launch to launch.  Both forms run the same
 // device function per step, so their results are bitwise identical.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "ag.h"
 #include "ag_internal.h"
@@ -100,8 +102,14 @@ __device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, l
 // The tiles of one block.  UNI (per-step kernels of a single-group launch):
 // the one group entry is loaded ahead of the state and written to LDS
 // without the group search and its extra barrier.
-template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS, bool TRK, bool UNI>
+template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK, bool UNI>
 __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* loff, int* sh) {
+    // RST: 0 no resets; 1 resets (per-step form: found and redrawn here; fused
+    // form: from the event kernels, events past the buffer redrawn here); 2
+    // fused form with every event of the launch in the buffer (no redraw code)
+    constexpr bool RESET = RST != 0;
+    constexpr bool EV = RESET && !ONE;
+    constexpr bool FB = !(EV && RST == 2);
     const int B = blockDim.x;
     const long long TILE = (long long)B * VPL;
     const long long tbase = a.d_step ? (*a.d_step + a.t_off) : a.t0;
@@ -156,6 +164,26 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
 #pragma unroll
             for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + il];
         }
+        // fused launches with resets: this launch's reset events of each lane
+        // (bit mask over the k steps, first event index) and the first
+        // event's redrawn state, fetched now so that its use costs nothing
+        unsigned long long evb[VPL];
+        long long evo[VPL];
+        int evr[VPL];
+        float pre[VPL][16];
+        if constexpr (EV) {
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                const long long il = act[v] ? idx[v] : a.n - 1;
+                evb[v] = act[v] ? a.ev.bits[il] : 0ull;
+                evo[v] = a.ev.off[il];
+                evr[v] = 0;
+                if (evb[v] != 0 && evo[v] < a.ev.cap) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) pre[v][r] = a.ev.data[r * a.ev.cap + evo[v]];
+                }
+            }
+        }
         int cnt = 1;
         if constexpr (UNI) {
             lds[e0] = te0;
@@ -180,9 +208,12 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         float u[VPL][RotorClass<NR>::NR];
         uint4 mw[VPL];
         long long mblk = -1;
-        for (int st = 0; st < K; ++st) {
-            const bool out_step = want_out && st == K - 1;
-            if constexpr (RESET) {
+        // one step of every lane; OUT: the step that writes the wrench and rotor
+        // outputs (the launch's last), peeled off the loop so that the loop
+        // does not carry its registers
+        auto run_step = [&](const int st, auto out_tag) {
+            constexpr bool OUT = decltype(out_tag)::value;
+            if constexpr (RESET && ONE) {
                 // reset words of four consecutive steps come from one Philox call
                 const long long tb = (tbase + st) >> 2;
                 if (tb != mblk) {
@@ -197,9 +228,30 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                 if (!act[v]) continue;
                 if constexpr (RESET) {
                     const uint32_t gi = a.index_base + (uint32_t)idx[v];
-                    if (mask_hit(mw[v], tbase + st, a.thr)) {
+                    bool hit;
+                    if constexpr (EV) hit = (evb[v] >> st) & 1ull;
+                    else hit = mask_hit(mw[v], tbase + st, a.thr);
+                    if (hit) {
                         float gx, gy, gz;
-                        redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
+                        if constexpr (EV) {
+                            const long long e = evo[v] + evr[v]++;
+                            if (e < a.ev.cap) {
+#pragma unroll
+                                for (int r = 0; r < 13; ++r) s[v][r] = pre[v][r];
+                                gx = pre[v][13];
+                                gy = pre[v][14];
+                                gz = pre[v][15];
+                            } else if constexpr (FB) {   // past the event buffer: redraw here
+                                redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
+                            }
+                            // the vehicle's next event of this launch, if any
+                            if (st + 1 < 64 && (evb[v] >> (st + 1)) != 0 && e + 1 < a.ev.cap) {
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) pre[v][r] = a.ev.data[r * a.ev.cap + e + 1];
+                            }
+                        } else {
+                            redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
+                        }
                         if (C[v].mode == 0) set_position_goal(C[v], gx, gy, gz);
                         if (a.goal) {
                             a.goal[idx[v]] = gx;
@@ -211,14 +263,17 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                     }
                 }
                 int ns;
-                if (out_step) ns = step<NR, true, true, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
+                if constexpr (OUT) ns = step<NR, true, true, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
                 else ns = step<NR, false, false, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
                 if constexpr (OBS) {
                     c_sat += ns;
                     sat_last[v] = ns;
                 }
             }
-        }
+        };
+        const int k_loop = want_out ? K - 1 : K;
+        for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{});
+        if (want_out) run_step(K - 1, std::true_type{});
 
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
@@ -289,19 +344,25 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
     }
 }
 
-template <int NR, bool VP, bool RESET, int VPL, bool ONE, bool OBS, bool TRK>
+template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK>
 __global__ __launch_bounds__(512) void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
     int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
     __shared__ int sh[2];
+    if constexpr (RST != 0 && !ONE) {
+        // both event variants are launched; the one that does not match the
+        // launch's event count leaves at once (a uniform test)
+        const bool fits = *a.ev.total <= a.ev.cap;
+        if (fits != (RST == 2)) return;
+    }
     if constexpr (ONE) {
         if (a.n_groups == 1) {     // uniform across the grid
-            step_tiles<NR, VP, RESET, VPL, ONE, OBS, TRK, true>(a, lds, loff, sh);
+            step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, true>(a, lds, loff, sh);
             return;
         }
     }
-    step_tiles<NR, VP, RESET, VPL, ONE, OBS, TRK, false>(a, lds, loff, sh);
+    step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, false>(a, lds, loff, sh);
 }
 
 // ---- statistics fold: slots -> cumulative accumulator (one block) ---------
@@ -442,6 +503,119 @@ __global__ __launch_bounds__(kResetBlock) void k_reset_scatter(ScatterArgs a) {
     if (m) a.indices[a.offsets[blockIdx.x] + before + rank_in_wave] = (int32_t)i;
 }
 
+// ---- reset events of a fused launch -----------------------------------------
+// The counter-based reset decisions of a launch's k steps do not depend on the
+// state, so they are found, counted, listed and redrawn before the launch by
+// dense kernels (one lane per vehicle, then one lane per event) instead of in
+// a divergent branch of the step loop.
+
+__device__ __forceinline__ long long launch_t0(const StepArgs& a) {
+    return a.d_step ? (*a.d_step + a.t_off) : a.t0;
+}
+
+__global__ __launch_bounds__(kResetBlock) void k_ev_mask(StepArgs a) {
+    __shared__ int wsum[kResetBlock / 64];
+    const long long i = (long long)blockIdx.x * kResetBlock + threadIdx.x;
+    unsigned long long bits = 0;
+    if (i < a.n) {
+        const long long tb0 = launch_t0(a);
+        const uint32_t gi = a.index_base + (uint32_t)i;
+        long long mblk = -1;
+        uint4 mw = make_uint4(0u, 0u, 0u, 0u);
+        for (int j = 0; j < a.k; ++j) {
+            const long long t = tb0 + j;
+            if ((t >> 2) != mblk) {
+                mblk = t >> 2;
+                mw = mask_block(gi, (uint64_t)mblk, a.key0, a.key1);
+            }
+            if (mask_hit(mw, t, a.thr)) bits |= 1ull << j;
+        }
+        a.ev.bits[i] = bits;
+    }
+    const int c = wave_sum((int)__popcll(bits));
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kResetBlock / 64; ++w) t += wsum[w];
+        a.ev.block_counts[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the per-block event counts in place and their total (one
+// block, fixed order, 64-bit: totals may exceed 2^31).
+__global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
+    __shared__ long long buf[1024];
+    __shared__ long long carry;
+    const int nblocks = (int)((a.n + kResetBlock - 1) / kResetBlock);
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 1024) {
+        const int j = base + threadIdx.x;
+        const long long v = j < nblocks ? a.ev.block_counts[j] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const long long t = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (j < nblocks) a.ev.block_counts[j] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.ev.total = carry;
+}
+
+// Per-vehicle first-event index (clamped to cap: events past cap are redrawn
+// in the step loop) and the event list in vehicle-major, step-minor order.
+__global__ __launch_bounds__(kResetBlock) void k_ev_scatter(StepArgs a) {
+    __shared__ int wtot[kResetBlock / 64];
+    const long long i = (long long)blockIdx.x * kResetBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long bits = i < a.n ? a.ev.bits[i] : 0ull;
+    const int c = __popcll(bits);
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wid] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wid; ++w) before += wtot[w];
+    if (i >= a.n) return;
+    const long long off = a.ev.block_counts[blockIdx.x] + before + (incl - c);
+    a.ev.off[i] = (int32_t)(off < a.ev.cap ? off : a.ev.cap);
+    unsigned long long b = bits;
+    for (long long e = off; b != 0 && e < a.ev.cap; ++e) {
+        const int j = __builtin_ctzll(b);
+        b &= b - 1;
+        a.ev.list[e] = (i << 6) | j;
+    }
+}
+
+// One lane per listed event: the redrawn state and goal.
+__global__ __launch_bounds__(256) void k_ev_redraw(StepArgs a) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long total = *a.ev.total;
+    if (e >= total || e >= a.ev.cap) return;
+    const long long code = a.ev.list[e];
+    const long long i = code >> 6;
+    const int j = (int)(code & 63);
+    float s[13], gx, gy, gz;
+    redraw(s, gx, gy, gz, a.index_base + (uint32_t)i, launch_t0(a) + j, a.key0, a.key1, a.lo, a.hi);
+    const long long cap = a.ev.cap;
+#pragma unroll
+    for (int r = 0; r < 13; ++r) a.ev.data[r * cap + e] = s[r];
+    a.ev.data[13 * cap + e] = gx;
+    a.ev.data[14 * cap + e] = gy;
+    a.ev.data[15 * cap + e] = gz;
+}
+
 // ---- obstacle poses at environment reset -----------------------------------
 // One lane per (environment, obstacle slot).  Position: fraction of the env
 // box per axis drawn in [frac_lo, frac_hi]; attitude: Z-Y-X Euler angles in
@@ -531,34 +705,43 @@ const void* observe_kernel() { return reinterpret_cast<const void*>(&k_observe);
 // ---- kernel lookup ---------------------------------------------------------
 // Kernels with trajectories (mode 4) exist for one vehicle per lane and for
 // the quad and mixed rotor classes only.
-template <int NR, bool VP, bool RESET, bool OBS, bool TRK>
+template <int NR, bool VP, int RST, bool OBS, bool TRK>
 static const void* pick_shape(int vpl, bool one) {
-    if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, true, OBS, TRK>);
-    if constexpr (!TRK) {
-        if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 2, false, OBS, TRK>);
+    if constexpr (RST != 2) {
+        if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 1, true, OBS, TRK>);
     }
-    return reinterpret_cast<const void*>(&k_step<NR, VP, RESET, 1, false, OBS, TRK>);
+    if constexpr (!TRK) {
+        if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 2, false, OBS, TRK>);
+    }
+    return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 1, false, OBS, TRK>);
 }
 
-template <int NR, bool VP, bool RESET, bool TRK>
+template <int NR, bool VP, int RST, bool TRK>
 static const void* pick_obs(int vpl, bool one, bool obs) {
-    return obs ? pick_shape<NR, VP, RESET, true, TRK>(vpl, one) : pick_shape<NR, VP, RESET, false, TRK>(vpl, one);
+    return obs ? pick_shape<NR, VP, RST, true, TRK>(vpl, one) : pick_shape<NR, VP, RST, false, TRK>(vpl, one);
+}
+
+template <int NR, bool VP, bool TRK>
+static const void* pick_rst(int rst, int vpl, bool one, bool obs) {
+    if (rst == 2) return pick_obs<NR, VP, 2, TRK>(vpl, one, obs);
+    if (rst == 1) return pick_obs<NR, VP, 1, TRK>(vpl, one, obs);
+    return pick_obs<NR, VP, 0, TRK>(vpl, one, obs);
 }
 
 template <int NR, bool TRK>
-static const void* pick_nr(bool vp, bool reset, int vpl, bool one, bool obs) {
-    if (vp) return reset ? pick_obs<NR, true, true, TRK>(vpl, one, obs) : pick_obs<NR, true, false, TRK>(vpl, one, obs);
-    return reset ? pick_obs<NR, false, true, TRK>(vpl, one, obs) : pick_obs<NR, false, false, TRK>(vpl, one, obs);
+static const void* pick_nr(bool vp, int rst, int vpl, bool one, bool obs) {
+    return vp ? pick_rst<NR, true, TRK>(rst, vpl, one, obs) : pick_rst<NR, false, TRK>(rst, vpl, one, obs);
 }
 
-const void* step_kernel(int nr_class, bool vp, bool reset, int vpl, bool one_step, bool obs, bool trk) {
-    if (trk) return nr_class == 4 ? pick_nr<4, true>(vp, reset, vpl, one_step, obs)
-                                  : pick_nr<0, true>(vp, reset, vpl, one_step, obs);
+const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk) {
+    if (rst == 2 && one_step) return nullptr;
+    if (trk) return nr_class == 4 ? pick_nr<4, true>(vp, rst, vpl, one_step, obs)
+                                  : pick_nr<0, true>(vp, rst, vpl, one_step, obs);
     switch (nr_class) {
-        case 4: return pick_nr<4, false>(vp, reset, vpl, one_step, obs);
-        case 6: return pick_nr<6, false>(vp, reset, vpl, one_step, obs);
-        case 8: return pick_nr<8, false>(vp, reset, vpl, one_step, obs);
-        default: return pick_nr<0, false>(vp, reset, vpl, one_step, obs);
+        case 4: return pick_nr<4, false>(vp, rst, vpl, one_step, obs);
+        case 6: return pick_nr<6, false>(vp, rst, vpl, one_step, obs);
+        case 8: return pick_nr<8, false>(vp, rst, vpl, one_step, obs);
+        default: return pick_nr<0, false>(vp, rst, vpl, one_step, obs);
     }
 }
 
@@ -570,5 +753,9 @@ const void* reset_mask_kernel() { return reinterpret_cast<const void*>(&k_reset_
 const void* reset_scan_kernel() { return reinterpret_cast<const void*>(&k_reset_scan); }
 const void* reset_scatter_kernel() { return reinterpret_cast<const void*>(&k_reset_scatter); }
 const void* clear_slots_kernel() { return reinterpret_cast<const void*>(&k_clear_slots); }
+const void* ev_mask_kernel() { return reinterpret_cast<const void*>(&k_ev_mask); }
+const void* ev_scan_kernel() { return reinterpret_cast<const void*>(&k_ev_scan); }
+const void* ev_scatter_kernel() { return reinterpret_cast<const void*>(&k_ev_scatter); }
+const void* ev_redraw_kernel() { return reinterpret_cast<const void*>(&k_ev_redraw); }
 
 }  // namespace ag

@@ -53,6 +53,18 @@ __device__ __forceinline__ const float* rollout_stage(const RolloutArgs& a, floa
     return lds + j * GSTRIDE;
 }
 
+// The vehicle's group entry held in registers for the whole rollout: at the
+// rollouts' sizes a SIMD runs one or two wavefronts, too few to hide the LDS
+// latency of the allocation table on every step.
+struct EntryRegs {
+    float e[GSTRIDE];
+};
+
+__device__ __forceinline__ void copy_entry(EntryRegs& g, const float* gt) {
+#pragma unroll
+    for (int k = 0; k < GSTRIDE; ++k) g.e[k] = gt[k];
+}
+
 template <int NR>
 __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     extern __shared__ float4 lds4[];
@@ -61,8 +73,11 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     __shared__ int sh[2];
     const long long base = (long long)blockIdx.x * blockDim.x;
     const long long i = base + threadIdx.x;
-    const float* gt = rollout_stage(a, lds, loff, sh, base, base + blockDim.x < a.n ? base + blockDim.x : a.n, i);
+    const float* gl = rollout_stage(a, lds, loff, sh, base, base + blockDim.x < a.n ? base + blockDim.x : a.n, i);
     if (i >= a.n) return;
+    EntryRegs ge;
+    copy_entry(ge, gl);
+    const float* gt = ge.e;
     const long long ld = a.ld, n = a.n;
     float s[13];
 #pragma unroll
@@ -147,7 +162,10 @@ __global__ __launch_bounds__(128) void k_rollout_adj(RolloutArgs a) {
     const bool reverse_wave = threadIdx.x < 64;       // uniform per wavefront
     const long long base = (long long)blockIdx.x * 64;
     const long long i = base + (threadIdx.x & 63);
-    const float* gt = rollout_stage(a, lds, loff, sh, base, base + 64 < a.n ? base + 64 : a.n, i);
+    const float* gl = rollout_stage(a, lds, loff, sh, base, base + 64 < a.n ? base + 64 : a.n, i);
+    EntryRegs ge;
+    copy_entry(ge, gl);
+    const float* gt = ge.e;
     const bool act = i < a.n;
     const long long ld = a.ld;
     const long long buf = (long long)a.m * 13 * a.n;   // floats per tape buffer

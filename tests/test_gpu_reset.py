@@ -101,6 +101,34 @@ def test_automatic_resets_equal_explicit_resets(policy):
     b.close()
 
 
+def test_automatic_resets_past_the_event_buffer():
+    """Fused launches find their resets before the launch and hold one event
+    per vehicle; with p = 0.3 and k = 64 most events of a launch lie past that
+    buffer and are redrawn in the step loop.  Both routes together still equal
+    explicit ag_reset + ag_step(1), goals included."""
+    need_gpu()
+    wl = mixed(5_001, 43)
+    wl.reset_prob = 0.3
+    goal_a = torch.zeros(3, wl.n)
+    goal_b = torch.zeros(3, wl.n)
+    a = make_sim(wl, auto_reset=True, goal=goal_a)
+    a.set_exec(kind=1, block=128, vpl=1, k=64, use_graph=1)
+    a.step(64)
+    a.step(6)
+    a.sync()
+    b = make_sim(wl, goal=goal_b)
+    b.set_exec(kind=0, block=256, use_graph=0)
+    for t in range(70):
+        b.reset(step=t)
+        b.step(1)
+    b.sync()
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.target, b.target)
+    assert torch.equal(a.goal, b.goal)
+    a.close()
+    b.close()
+
+
 def test_full_size_mask_bit_exact():
     """4,194,304 vehicles (the large randomized rollout): the reset mask and
     indices of one step are bit-exact at full size."""
