@@ -170,7 +170,6 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         unsigned long long evb[VPL];
         long long evo[VPL];
         int evr[VPL];
-        float pre[VPL][16];
         if constexpr (EV) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
@@ -178,10 +177,6 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                 evb[v] = act[v] ? a.ev.bits[il] : 0ull;
                 evo[v] = a.ev.off[il];
                 evr[v] = 0;
-                if (evb[v] != 0 && evo[v] < a.ev.cap) {
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) pre[v][r] = a.ev.data[r * a.ev.cap + evo[v]];
-                }
             }
         }
         int cnt = 1;
@@ -236,18 +231,14 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                         if constexpr (EV) {
                             const long long e = evo[v] + evr[v]++;
                             if (e < a.ev.cap) {
+                                const float* ed = a.ev.data + e;
 #pragma unroll
-                                for (int r = 0; r < 13; ++r) s[v][r] = pre[v][r];
-                                gx = pre[v][13];
-                                gy = pre[v][14];
-                                gz = pre[v][15];
+                                for (int r = 0; r < 13; ++r) s[v][r] = ed[r * a.ev.cap];
+                                gx = ed[13 * a.ev.cap];
+                                gy = ed[14 * a.ev.cap];
+                                gz = ed[15 * a.ev.cap];
                             } else if constexpr (FB) {   // past the event buffer: redraw here
                                 redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
-                            }
-                            // the vehicle's next event of this launch, if any
-                            if (st + 1 < 64 && (evb[v] >> (st + 1)) != 0 && e + 1 < a.ev.cap) {
-#pragma unroll
-                                for (int r = 0; r < 16; ++r) pre[v][r] = a.ev.data[r * a.ev.cap + e + 1];
                             }
                         } else {
                             redraw(s[v], gx, gy, gz, gi, tbase + st, a.key0, a.key1, a.lo, a.hi);
@@ -345,7 +336,8 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
 }
 
 template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK>
-__global__ __launch_bounds__(512) void k_step(StepArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RST == 2 && VPL == 1 ? 4 : 1)))
+void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
     int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
