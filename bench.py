@@ -33,9 +33,9 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "6be7e70228496d82",
-    "per_step_bytes": 127017742.9,
-    "fused_bytes": 126983858.9,
+    "src": "1241d704d030cb57",
+    "per_step_bytes": 128030976.0,
+    "fused_bytes": 126991810.0,
     "fused_valu_per_vstep": 189.7,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }

@@ -535,30 +535,32 @@ __global__ __launch_bounds__(kResetBlock) void k_ev_mask(StepArgs a) {
 }
 
 // Exclusive scan of the per-block event counts in place and their total (one
-// block, fixed order, 64-bit: totals may exceed 2^31).
+// block, fixed order, 64-bit: totals may exceed 2^31).  Each thread sums a
+// contiguous run of counts, one block-wide scan combines the runs, and each
+// thread writes its run's offsets.
 __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
     __shared__ long long buf[1024];
-    __shared__ long long carry;
     const int nblocks = (int)((a.n + kResetBlock - 1) / kResetBlock);
-    if (threadIdx.x == 0) carry = 0;
+    const int per = (nblocks + 1023) / 1024;
+    const int b0 = (int)threadIdx.x * per;
+    const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    long long run = 0;
+    for (int j = b0; j < b1; ++j) run += a.ev.block_counts[j];
+    buf[threadIdx.x] = run;
     __syncthreads();
-    for (int base = 0; base < nblocks; base += 1024) {
-        const int j = base + threadIdx.x;
-        const long long v = j < nblocks ? a.ev.block_counts[j] : 0;
-        buf[threadIdx.x] = v;
+    for (int o = 1; o < 1024; o <<= 1) {
+        const long long t = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
         __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const long long t = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (j < nblocks) a.ev.block_counts[j] = carry + buf[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += buf[1023];
+        buf[threadIdx.x] += t;
         __syncthreads();
     }
-    if (threadIdx.x == 0) *a.ev.total = carry;
+    long long off = buf[threadIdx.x] - run;
+    for (int j = b0; j < b1; ++j) {
+        const long long c = a.ev.block_counts[j];
+        a.ev.block_counts[j] = off;
+        off += c;
+    }
+    if (threadIdx.x == 1023) *a.ev.total = buf[1023];
 }
 
 // Per-vehicle first-event index (clamped to cap: events past cap are redrawn
