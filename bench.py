@@ -33,10 +33,10 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "1241d704d030cb57",
-    "per_step_bytes": 128030976.0,
-    "fused_bytes": 126991810.0,
-    "fused_valu_per_vstep": 189.7,
+    "src": "a6856f3e7768236c",
+    "per_step_bytes": 126996212.1,
+    "fused_bytes": 126991059.7,
+    "fused_valu_per_vstep": 187.1,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
@@ -141,7 +141,7 @@ def bench_uneven(sync):
     from paper_2305_16510_amd.sim import Sim
     wl = workloads.c3_uneven()
     sim = Sim.from_workload(wl, autotune_scratch=True)
-    tuned = sim.autotune(32)
+    tuned = sim.autotune(512)
     sim.prepare(wl.steps)
     sim.raw_step(wl.steps)
     sync()
@@ -271,7 +271,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=1_048_576)
-    ap.add_argument("--probe-steps", type=int, default=64)
+    ap.add_argument("--probe-steps", type=int, default=512,
+                    help="steps per autotuning trial (also the largest k tried)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-step", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -405,7 +406,8 @@ def main():
                    "global_batch": wl.n, "parallelism": "none (1 GPU)", "exec": tuned},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_PEAK_TFLOPS,
-                     "traffic": COUNTERS["fused_bytes"] if valid and k == 64 else None,
+                     # one load and one store of the state per launch, whatever k
+                     "traffic": COUNTERS["fused_bytes"] if valid else None,
                      "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
                      "steps_per_launch": k, "flops_per_vehicle_step": FLOPS_PER_VSTEP,
                      "valu_instr_per_vehicle_step": COUNTERS["fused_valu_per_vstep"] if valid else None,

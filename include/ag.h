@@ -186,8 +186,10 @@ ag_status ag_prepare(ag_handle h, int32_t n_steps);
 ag_status ag_set_exec(ag_handle h, const ag_exec* e);
 ag_status ag_get_exec(ag_handle h, ag_exec* e);
 
-/* Time candidate fused policies (block, vehicles per lane, k, grid) for
- * probe_steps steps each and keep the fastest; synchronises the stream.  With
+/* Time candidate fused policies (block 64..512, vehicles per lane 1 or 2,
+ * k in 4..512 up to probe_steps, grid one block per tile or a persistent
+ * multiple of the CU count) for probe_steps steps each and keep the fastest;
+ * synchronises the stream.  With
  * autotune_scratch the probes write scratch buffers, so the state is
  * untouched; without it the call returns AG_E_STATE. */
 ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen);

@@ -699,7 +699,7 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     int occ_blocks_per_cu = 0;
     const int blocks[] = {64, 128, 256, 512};
     const int vpls[] = {1, 2};
-    const int ks[] = {4, 8, 16, 32, 64};
+    const int ks[] = {4, 8, 16, 32, 64, 128, 256, 512};
     ag_exec best = h->exec;
     float best_ms = 1e30f;
     const long long saved_t = h->t;
