@@ -85,3 +85,38 @@ def test_full_resolution_sampled_cameras():
     emax, mism, off_edge = compare(d[idx], ref, 10.0)
     print("full res: max rel err off silhouettes %.2e, mismatched pixels %.3f%%" % (emax, 100 * mism))
     assert emax <= 1e-4 and mism < 0.005 and off_edge == 0
+
+
+@pytest.mark.parametrize("maxd", [2.5, 10.0])
+def test_tile_culling_short_range_and_inside_obstacles(maxd):
+    """Cases aimed at the per-tile obstacle culling: a short max_depth (most
+    obstacles lie beyond it and are culled by depth) and cameras inside an
+    obstacle (vehicles 0 and 1 sit at the centre of one of their obstacles,
+    so the tile cone starts inside a bounding sphere)."""
+    need_gpu()
+    from paper_2305_16510_amd.sim import Sim
+    n, n_obs, W, H = 8, 20, 128, 64
+    wl = workloads.c1_parity(n=n, seed=82)
+    wl.state0[0:3] = np.array([[0.5], [5.0], [1.5]], np.float32) + wl.state0[0:3] * 0.2
+    sim = Sim.from_workload(wl)
+    shapes, slots = scene(n, n_obs, 82)
+    obst = torch.zeros(7, n * n_obs, device="cuda")
+    obst[3] = 1.0
+    sim.randomize_obstacles(slots, obst, step=3, box_lo=(0.0, 0.0, 0.0), box_hi=(10.0, 10.0, 3.0))
+    for i in (0, 1):
+        sim.state[0:3, i] = obst[0:3, i * n_obs + 3 * i]
+    mount_q = Rotation.from_euler("y", 8, degrees=True).as_quat()[[3, 0, 1, 2]]
+    depth = sim.render_depth(shapes, obst, W, H, 1.5, maxd, floor_z=0.0, mount_pos=(0.1, 0.0, 0.05),
+                             mount_quat=tuple(mount_q))
+    sim.sync()
+    st = sim.state.cpu().numpy().T.astype(np.float64)
+    ob = obst.cpu().numpy().T.astype(np.float64).reshape(n, n_obs, 7)
+    d = depth.cpu().numpy()
+    sim.close()
+    ref = raycast.render(st[:, 0:3], st[:, 6:10], np.array([0.1, 0.0, 0.05]), mount_q, shapes.astype(np.float64),
+                         ob, 0.0, W, H, 1.5, maxd)
+    emax, mism, off_edge = compare(d, ref, maxd)
+    print("max_depth %.1f: max rel err off silhouettes %.2e, mismatched pixels %.3f%%, at max_depth %.1f%%" %
+          (maxd, emax, 100 * mism, 100 * (ref == maxd).mean()))
+    assert emax <= 1e-4 and mism < 0.005 and off_edge == 0
+    assert (ref[0:2] < maxd).mean() > 0.5          # the cameras inside obstacles see their walls
