@@ -202,6 +202,25 @@ bool build_group_entry(const ag_group_desc& g, float* e) {
     }
     for (int k = 0; k < AG_NGAINS; ++k) e[G_GAINS + k] = g.gains[k];
     e[G_NR] = (float)n;
+    if (n == 4) {
+        // the kernels' quad butterflies assume that every row of the FP32
+        // tables is one magnitude with the signs of the X layout
+        static const float sx[4] = {1, 1, -1, -1}, sy[4] = {-1, 1, 1, -1}, sz[4] = {1, -1, 1, -1};
+        const float* p0 = e + G_APINV;
+        const float* c0 = e + G_ACOL;
+        for (int i = 0; i < 4; ++i) {
+            const float* p = p0 + 4 * i;
+            const float* c = c0 + 4 * i;
+            if (p[0] != p0[0] || p[1] != sx[i] * p0[1] || p[2] != sy[i] * p0[1] || p[3] != sz[i] * p0[3] ||
+                c[0] != 1.0f || c[1] != sx[i] * c0[1] || c[2] != sy[i] * c0[1] || c[3] != sz[i] * c0[3])
+                return false;
+        }
+        e[G_Q_F] = p0[0];
+        e[G_Q_XY] = p0[1];
+        e[G_Q_Z] = p0[3];
+        e[G_Q_S] = c0[1];
+        e[G_Q_CT] = c0[3];
+    }
     return true;
 }
 

@@ -20,7 +20,8 @@
 //   * dt, the mass, 1/J and the 1/2 of eq. (3) are folded into per-vehicle
 //     constants, which a fused launch computes once (loop-invariant).
 // Allocation uses a unit-arm table per rotor layout: u = clip(A1^+ (f, M_x/l,
-// M_y/l, M_z)), applied wrench (sum u, l (A1 u)_1, l (A1 u)_2, (A1 u)_3).
+// M_y/l, M_z)), applied wrench (sum u, l (A1 u)_1, l (A1 u)_2, (A1 u)_3);
+// for the quad X layout both products are 4-point butterflies.
 // Integration is semi-implicit Euler with quaternion renormalisation.
 #pragma once
 
@@ -47,6 +48,10 @@ constexpr int G_J = 70;           // 3
 constexpr int G_JINV = 73;        // 3
 constexpr int G_GAINS = 76;       // 10
 constexpr int G_NR = 86;          // rotor count, as float
+// quad-X layout only: the unit-arm A^+ and A are one +-1 pattern scaled per
+// row, so the kernels use butterflies on these five scales instead of the
+// rows above: A^+ thrust / x-y moment / yaw coefficients, sin(pi/4), c_tau
+constexpr int G_Q_F = 87, G_Q_XY = 88, G_Q_Z = 89, G_Q_S = 90, G_Q_CT = 91;
 
 // ---- per-vehicle parameter rows (vparams) ---------------------------------
 constexpr int VP_MASS = 0, VP_J = 1, VP_GAINS = 4, VP_ARM = 14, VP_UMAX = 15;
@@ -54,9 +59,13 @@ constexpr int VP_MASS = 0, VP_J = 1, VP_GAINS = 4, VP_ARM = 14, VP_UMAX = 15;
 struct Params {
     float m, inv_m;
     float J0, J1, J2, Ji0, Ji1, Ji2;
+    float dJ0, dJ1, dJ2;       // J2 - J1, J0 - J2, J1 - J0
     float kx_xy, kx_z, kv_xy, kv_z;
     float kR0, kR1, kR2, kW0, kW1, kW2;
     float arm, inv_arm, umin, umax;
+    // quad butterflies: u = clip(H^T (cq_f f, cq_x M_x, cq_x M_y, cq_z M_z)),
+    // applied moment (armq X0, armq X1, ctq X2) with X the butterfly sums
+    float cq_f, cq_x, cq_z, armq, ctq;
     int nr;
 };
 
@@ -126,6 +135,14 @@ AG_DEV void load_params(Params& P, const float* __restrict__ gt, const float* __
         P.inv_arm = gt[G_INV_ARM];
         P.umax = gt[G_UMAX];
     }
+    P.dJ0 = P.J2 - P.J1;
+    P.dJ1 = P.J0 - P.J2;
+    P.dJ2 = P.J1 - P.J0;
+    P.cq_f = gt[G_Q_F];
+    P.cq_x = gt[G_Q_XY] * P.inv_arm;
+    P.cq_z = gt[G_Q_Z];
+    P.armq = P.arm * gt[G_Q_S];
+    P.ctq = gt[G_Q_CT];
 }
 
 // Reciprocal square root as the single hardware instruction (1 ulp); every
@@ -297,10 +314,9 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     float eW2 = w2 - psidot * R22;
 
     // ---- gyroscopic term Omega x J Omega ------------------------------------
-    const float JW0 = P.J0 * w0, JW1 = P.J1 * w1, JW2 = P.J2 * w2;
-    const float gy0 = w1 * JW2 - w2 * JW1;
-    const float gy1 = w2 * JW0 - w0 * JW2;
-    const float gy2 = w0 * JW1 - w1 * JW0;
+    // for diagonal J its components are (J2 - J1) w1 w2, (J0 - J2) w2 w0 and
+    // (J1 - J0) w0 w1 (exactly zero about a symmetry axis)
+    const float w12 = w1 * w2, w20 = w2 * w0, w01 = w0 * w1;
 
     // ---- mode 4: full geometric tracking law (kernels with trajectories) ----
     float ff0 = 0.0f, ff1 = 0.0f, ff2 = 0.0f;
@@ -356,65 +372,127 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     }
 
     // ---- M = -kR e_R - kW e_Omega + Omega x J Omega, eq. (5) ---------------
+    // The allocation takes M scaled per axis, (cq_x M_x, cq_x M_y, cq_z M_z)
+    // for the quad butterflies and (M_x / l, M_y / l, M_z) for the table, so
+    // the law is evaluated directly in those units with pre-scaled constants
+    // (loop-invariant products); the rate update below takes the scaled
+    // gyroscopic term with dt J^-1 divided by the same scales.
+    const bool quad = NRC == 4 || (MIXED && P.nr == 4);
+    const float s01 = quad ? P.cq_x : P.inv_arm;
+    const float s2 = quad ? P.cq_z : 1.0f;
     const float hkR0 = 0.5f * P.kR0, hkR1 = 0.5f * P.kR1, hkR2 = 0.5f * P.kR2;
-    float M0 = gy0 - hkR0 * dR0 - P.kW0 * eW0;
-    float M1 = gy1 - hkR1 * dR1 - P.kW1 * eW1;
-    float M2 = gy2 - hkR2 * dR2 - P.kW2 * eW2;
+    const float gs0 = (s01 * P.dJ0) * w12, gs1 = (s01 * P.dJ1) * w20, gs2 = (s2 * P.dJ2) * w01;
+    float Ms0 = gs0 - (s01 * hkR0) * dR0 - (s01 * P.kW0) * eW0;
+    float Ms1 = gs1 - (s01 * hkR1) * dR1 - (s01 * P.kW1) * eW1;
+    float Ms2 = gs2 - (s2 * hkR2) * dR2 - (s2 * P.kW2) * eW2;
     if constexpr (TRK) {
-        M0 -= ff0;
-        M1 -= ff1;
-        M2 -= ff2;
+        Ms0 -= s01 * ff0;
+        Ms1 -= s01 * ff1;
+        Ms2 -= s2 * ff2;
     }
     // mode 3 takes the commanded moment, an unknown mode a zero wrench (one
     // select per component against per-vehicle constants)
     const bool direct = m3 || !(m0 || m1 || m2 || m4);
-    M0 = direct ? (m3 ? C.t1 : 0.0f) : M0;
-    M1 = direct ? (m3 ? C.t2 : 0.0f) : M1;
-    M2 = direct ? (m3 ? C.t3 : 0.0f) : M2;
+    Ms0 = direct ? s01 * (m3 ? C.t1 : 0.0f) : Ms0;
+    Ms1 = direct ? s01 * (m3 ? C.t2 : 0.0f) : Ms1;
+    Ms2 = direct ? s2 * (m3 ? C.t3 : 0.0f) : Ms2;
 
     // ---- allocation and clamping ------------------------------------------
-    const float a1 = M0 * P.inv_arm, a2 = M1 * P.inv_arm;
-    float fa, S0, S1, S2;
+    // applied wrench (fa, k01 X0, k01 X1, k2 X2)
+    float fa, X0, X1, X2, k01, k2;
     int nsat = 0;
     float raws[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         raws[r] = 0.0f;
         if constexpr (WANT_U) u_out[r] = 0.0f;
-        // in a mixed launch, lanes with fewer rotors skip slots 4..7 (every
-        // layout has at least 4); a wavefront inside one group skips them
-        // entirely, and a skipped slot leaves the sums as a zero thrust would
-        if (MIXED && r >= 4 && r >= P.nr) continue;
-        const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
-        const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
-        const float raw = ap.x * f + ap.y * a1 + ap.z * a2 + ap.w * M2;
+    }
+    // clamp to [u_min, u_max] as one median-of-three
+    auto clamp_rotor = [&](int r, float raw) -> float {
         raws[r] = raw;
-        // clamp to [u_min, u_max] as one median-of-three
         const float u = __builtin_amdgcn_fmed3f(raw, P.umin, P.umax);
         nsat += (int)((raw < P.umin) | (raw > P.umax));
-        if (r == 0) {
-            fa = u * ac.x;
-            S0 = u * ac.y;
-            S1 = u * ac.z;
-            S2 = u * ac.w;
-        } else {
-            fa += u * ac.x;
-            S0 += u * ac.y;
-            S1 += u * ac.z;
-            S2 += u * ac.w;
-        }
         if constexpr (WANT_U) u_out[r] = u;
+        return u;
+    };
+    // Quad X (rotors at 45, 135, 225, 315 degrees, spins + - + -): rotor i's
+    // raw thrust is cq_f f + sx_i cq_x M_x + sy_i cq_x M_y + sz_i cq_z M_z with
+    // sx = (+ + - -), sy = (- + + -), sz = (+ - + -), and the applied wrench
+    // sums the thrusts with the same signs, so both products are 4-point
+    // butterflies (8 additions each instead of 16 multiply-adds).
+    auto quad_alloc = [&]() {
+        const float a = P.cq_f * f + Ms2, b = P.cq_f * f - Ms2;
+        const float c = Ms0 - Ms1, d = Ms0 + Ms1;
+        const float u0 = clamp_rotor(0, a + c), u1 = clamp_rotor(1, b + d);
+        const float u2 = clamp_rotor(2, a - c), u3 = clamp_rotor(3, b - d);
+        const float e = u0 + u2, o = u1 + u3, ge = u0 - u2, ho = u1 - u3;
+        fa = e + o;
+        X0 = ge + ho;
+        X1 = ho - ge;
+        X2 = e - o;
+        k01 = P.armq;
+        k2 = P.ctq;
+    };
+    // any layout: u = clip(A1^+ (f, M_x/l, M_y/l, M_z)), X = A1 u (rows 1..3)
+    auto table_alloc = [&]() {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            // in a mixed launch, lanes with fewer rotors skip slots 4..7 (every
+            // layout has at least 4); a wavefront inside one group skips them
+            // entirely, and a skipped slot leaves the sums as a zero thrust would
+            if (MIXED && r >= 4 && r >= P.nr) continue;
+            const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
+            const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
+            const float u = clamp_rotor(r, ap.x * f + ap.y * Ms0 + ap.z * Ms1 + ap.w * Ms2);
+            if (r == 0) {
+                fa = u * ac.x;
+                X0 = u * ac.y;
+                X1 = u * ac.z;
+                X2 = u * ac.w;
+            } else {
+                fa += u * ac.x;
+                X0 += u * ac.y;
+                X1 += u * ac.z;
+                X2 += u * ac.w;
+            }
+        }
+        k01 = P.arm;
+        k2 = 1.0f;
+    };
+    // every kernel that meets a quad takes the butterflies, so a quad group
+    // rounds identically in a quad-only and in a mixed launch
+    if constexpr (NRC == 4) {
+        quad_alloc();
+    } else if constexpr (MIXED) {
+        if (P.nr == 4) quad_alloc();
+        else table_alloc();
+    } else {
+        table_alloc();
     }
-    // applied wrench: (fa, l S0, l S1, S2)
     if constexpr (WANT_W) {
-        W->f = f; W->M0 = M0; W->M1 = M1; W->M2 = M2;
-        W->fa = fa; W->Ma0 = P.arm * S0; W->Ma1 = P.arm * S1; W->Ma2 = S2;
+        // the commanded moment in N m (the same law, unscaled)
+        float M0 = P.dJ0 * w12 - hkR0 * dR0 - P.kW0 * eW0;
+        float M1 = P.dJ1 * w20 - hkR1 * dR1 - P.kW1 * eW1;
+        float M2 = P.dJ2 * w01 - hkR2 * dR2 - P.kW2 * eW2;
+        if constexpr (TRK) {
+            M0 -= ff0;
+            M1 -= ff1;
+            M2 -= ff2;
+        }
+        W->f = f;
+        W->M0 = direct ? (m3 ? C.t1 : 0.0f) : M0;
+        W->M1 = direct ? (m3 ? C.t2 : 0.0f) : M1;
+        W->M2 = direct ? (m3 ? C.t3 : 0.0f) : M2;
+        W->fa = fa; W->Ma0 = k01 * X0; W->Ma1 = k01 * X1; W->Ma2 = k2 * X2;
     }
 
     // ---- semi-implicit Euler ----------------------------------------------
     // dt is folded into 1/m and J^-1 (loop-invariant products in a fused launch)
     const float dt_m = dt * P.inv_m, dtg = dt * g;
-    const float dtJi0 = dt * P.Ji0, dtJi1 = dt * P.Ji1, dtJi2 = dt * P.Ji2;
+    // (k01 X0 - gy0) dt/J0 = (k01 s01 X0 - gs0) (dt/J0) / s01, likewise for
+    // axes 1 and 2; loop-invariant constants
+    const float Ds0 = (dt * P.Ji0) / s01, Ds1 = (dt * P.Ji1) / s01, Ds2 = (dt * P.Ji2) / s2;
+    const float Ks01 = k01 * s01, Ks2 = k2 * s2;
     const float dva = fa * dt_m;
     const float nvx = dva * R02 + vx;
     const float nvy = dva * R12 + vy;
@@ -423,9 +501,9 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     s[1] = s[1] + dt * nvy;
     s[2] = s[2] + dt * nvz;
     s[3] = nvx; s[4] = nvy; s[5] = nvz;
-    const float nw0 = (P.arm * S0 - gy0) * dtJi0 + w0;
-    const float nw1 = (P.arm * S1 - gy1) * dtJi1 + w1;
-    const float nw2 = (S2 - gy2) * dtJi2 + w2;
+    const float nw0 = (Ks01 * X0 - gs0) * Ds0 + w0;
+    const float nw1 = (Ks01 * X1 - gs1) * Ds1 + w1;
+    const float nw2 = (Ks2 * X2 - gs2) * Ds2 + w2;
     s[10] = nw0; s[11] = nw1; s[12] = nw2;
     // q <- normalize(q + dt/2 q (x) (0, Omega+))
     // with h = (dt/2) Omega+ first: t = q + q (x) (0, h), one chain per component
@@ -479,21 +557,49 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         const float bfa = bacc * P.inv_m;
 
         // ---- allocation and clamp ----------------------------------------
-        const float bS1 = P.arm * bMa0, bS2 = P.arm * bMa1;
-        float bf = 0.0f, ba1 = 0.0f, ba2 = 0.0f, bM2 = 0.0f;
+        // adjoint of the applied wrench's sums X, then of the raw thrusts
+        // (clamp subgradient), then of (f, M): the transposes of the forward
+        // products, as butterflies for the quad
+        const float bX0 = k01 * bMa0, bX1 = k01 * bMa1, bX2 = k2 * bMa2;
+        float bf, bM0, bM1, bM2;
+        auto pass = [&](int r) { return (raws[r] >= P.umin) & (raws[r] <= P.umax); };
+        auto quad_rev = [&]() {
+            const float be = bfa + bX2, bo = bfa - bX2;
+            const float bge = bX0 - bX1, bho = bX0 + bX1;
+            const float br0 = pass(0) ? be + bge : 0.0f, br2 = pass(2) ? be - bge : 0.0f;
+            const float br1 = pass(1) ? bo + bho : 0.0f, br3 = pass(3) ? bo - bho : 0.0f;
+            const float ba = br0 + br2, bc = br0 - br2, bb = br1 + br3, bd = br1 - br3;
+            bf = P.cq_f * (ba + bb);
+            bM2 = P.cq_z * (ba - bb);
+            bM0 = P.cq_x * (bc + bd);
+            bM1 = P.cq_x * (bd - bc);
+        };
+        auto table_rev = [&]() {
+            float sf = 0.0f, ba1 = 0.0f, ba2 = 0.0f, sM2 = 0.0f;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
-            const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
-            const float bu = bfa * ac.x + bS1 * ac.y + bS2 * ac.z + bMa2 * ac.w;
-            const bool pass = (MIXED ? r < P.nr : true) & (raws[r] >= P.umin) & (raws[r] <= P.umax);
-            const float braw = pass ? bu : 0.0f;
-            bf += braw * ap.x;
-            ba1 += braw * ap.y;
-            ba2 += braw * ap.z;
-            bM2 += braw * ap.w;
+            for (int r = 0; r < NR; ++r) {
+                const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
+                const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
+                const float bu = bfa * ac.x + bX0 * ac.y + bX1 * ac.z + bX2 * ac.w;
+                const float braw = ((MIXED ? r < P.nr : true) & pass(r)) ? bu : 0.0f;
+                sf += braw * ap.x;
+                ba1 += braw * ap.y;
+                ba2 += braw * ap.z;
+                sM2 += braw * ap.w;
+            }
+            bf = sf;
+            bM0 = ba1 * P.inv_arm;
+            bM1 = ba2 * P.inv_arm;
+            bM2 = sM2;
+        };
+        if constexpr (NRC == 4) {
+            quad_rev();
+        } else if constexpr (MIXED) {
+            if (P.nr == 4) quad_rev();
+            else table_rev();
+        } else {
+            table_rev();
         }
-        float bM0 = ba1 * P.inv_arm, bM1 = ba2 * P.inv_arm;
         const bool ctl = m0 || m1 || m2;       // M depends on the state
         const bool frc = m0 || m1;             // f and the tilt depend on the state
         bM0 = ctl ? bM0 : 0.0f;
@@ -508,13 +614,10 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         const float beR0 = -P.kR0 * bM0, beR1 = -P.kR1 * bM1, beR2 = -P.kR2 * bM2;
         const float beW0 = -P.kW0 * bM0, beW1 = -P.kW1 * bM1, beW2 = -P.kW2 * bM2;
         bgy0 += bM0; bgy1 += bM1; bgy2 += bM2;
-        bw0 += -bgy1 * JW2 + bgy2 * JW1;
-        bw1 += bgy0 * JW2 - bgy2 * JW0;
-        bw2 += -bgy0 * JW1 + bgy1 * JW0;
-        const float bJW0 = bgy1 * w2 - bgy2 * w1, bJW1 = bgy2 * w0 - bgy0 * w2, bJW2 = bgy0 * w1 - bgy1 * w0;
-        bw0 += P.J0 * bJW0 + beW0;
-        bw1 += P.J1 * bJW1 + beW1;
-        bw2 += P.J2 * bJW2 + beW2;
+        const float cg0 = P.dJ0 * bgy0, cg1 = P.dJ1 * bgy1, cg2 = P.dJ2 * bgy2;
+        bw0 += cg1 * w2 + cg2 * w1 + beW0;
+        bw1 += cg0 * w2 + cg2 * w0 + beW1;
+        bw2 += cg0 * w1 + cg1 * w0 + beW2;
         bR20 -= psidot * beW0; bR21 -= psidot * beW1; bR22 -= psidot * beW2;
 
         // ---- attitude error, eq. (3) -------------------------------------
