@@ -271,7 +271,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=1_048_576)
-    ap.add_argument("--probe-steps", type=int, default=512,
+    ap.add_argument("--probe-steps", type=int, default=1024,
                     help="steps per autotuning trial (also the largest k tried)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-step", action="store_true")

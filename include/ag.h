@@ -175,7 +175,12 @@ ag_status ag_set_targets(ag_handle h, int64_t first, int64_t count, const int8_t
 
 /* Advance every vehicle by n_steps steps (controller, allocation, clamping,
  * integration; with auto_reset, the counter-based reset before each step),
- * asynchronously on the handle's stream, with the current execution policy. */
+ * asynchronously on the handle's stream, with the current execution policy.
+ * A fused call of 32 or more steps with one vehicle per lane, no trajectory
+ * buffer, no observers and no automatic resets first orders the vehicles of
+ * each group by command mode within segments of 4,096 (workspace), so that
+ * wavefronts of one mode run that mode's copy of the step loop; results are
+ * bitwise those of any other policy. */
 ag_status ag_step(ag_handle h, int32_t n_steps);
 
 /* Build and cache the HIP graph that ag_step(h, n_steps) will replay under
@@ -187,7 +192,7 @@ ag_status ag_set_exec(ag_handle h, const ag_exec* e);
 ag_status ag_get_exec(ag_handle h, ag_exec* e);
 
 /* Time candidate fused policies (block 64..512, vehicles per lane 1 or 2,
- * k in 4..512 up to probe_steps, grid one block per tile or a persistent
+ * k in 4..1024 up to probe_steps, grid one block per tile or a persistent
  * multiple of the CU count) for probe_steps steps each and keep the fastest;
  * synchronises the stream.  With
  * autotune_scratch the probes write scratch buffers, so the state is

@@ -29,6 +29,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct WsLayout {
     size_t gtab, goff, d_step, acc, slots, block_counts, mask, scratch, total;
     size_t ev_bits, ev_off, ev_bc, ev_total, ev_list, ev_data;
+    size_t perm;
     long long nslots, nblocks, ev_cap;
 };
 
@@ -44,6 +45,7 @@ WsLayout ws_layout(const ag_config* c) {
     L.nblocks = (c->n + kResetBlock - 1) / kResetBlock;
     L.block_counts = off; off = align_up(off + (size_t)L.nblocks * sizeof(int32_t));
     L.mask = off; off = align_up(off + (size_t)c->n);
+    L.perm = off; off = align_up(off + (size_t)c->n * sizeof(int32_t));
     L.scratch = off;
     if (c->autotune_scratch) off = align_up(off + (size_t)(AG_STATE_DIM + AG_TARGET_DIM) * c->ld * sizeof(float));
     // reset events of fused launches (automatic resets): room for n events per
@@ -91,6 +93,7 @@ struct ag_sim {
     long long* d_step;
     StatAcc* acc;
     StatSlot* slots;
+    int32_t* perm;          // mode order of fused launches
     int32_t* block_counts;
     uint8_t* mask_buf;
     float* scratch;
@@ -305,6 +308,19 @@ StepArgs base_args(ag_handle h) {
 // event kernels.
 bool uses_events(ag_handle h, const ag_exec& e) { return h->reset_on && e.kind == 1 && h->ev.cap > 0; }
 
+// Whether the fused launches of an ag_step of n_steps steps run in mode order
+// (their kernels have the mode-specialised step loops; the order costs one
+// pass over the modes per call, so short calls go without it).
+bool uses_order(ag_handle h, const ag_exec& e, int n_steps) {
+    return e.kind == 1 && e.vpl == 1 && h->cfg.traj == nullptr && n_steps >= kOrderMinSteps;
+}
+
+OrderArgs order_args(ag_handle h) {
+    return OrderArgs{h->cfg.mode, h->goff, h->perm, h->cfg.n, h->cfg.n_groups};
+}
+
+dim3 order_grid(ag_handle h) { return dim3((unsigned)((h->cfg.n + kOrderSeg - 1) / kOrderSeg)); }
+
 // The event kernels of one launch, in order (they take the launch's arguments).
 struct EvKernels {
     const void* fn[4];
@@ -374,6 +390,13 @@ ag_status run_direct(ag_handle h, const ag_exec& e, int n_steps, StepArgs a, boo
     if (!m.empty()) return set_err(h, AG_E_INVALID, m);
     a.span = s.span;
     a.d_step = nullptr;
+    a.perm = nullptr;
+    if (uses_order(h, e, n_steps)) {
+        OrderArgs o = order_args(h);
+        ag_status st = launch(h, mode_order_kernel(), order_grid(h), dim3(kOrderBlock), 0, &o);
+        if (st != AG_OK) return st;
+        a.perm = h->perm;
+    }
     const int k = e.kind == 0 ? 1 : e.k;
     for (int done = 0, j = 0; done < n_steps; done += k, ++j) {
         a.t0 = h->t + done;
@@ -419,6 +442,14 @@ ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
     a.d_step = h->d_step;
     const int k = h->exec.kind == 0 ? 1 : h->exec.k;
     hipGraphNode_t prev = nullptr, node = nullptr;
+    a.perm = nullptr;
+    if (uses_order(h, h->exec, n_steps)) {
+        OrderArgs o = order_args(h);
+        ag_status st = add_node(h, g, &node, nullptr, mode_order_kernel(), order_grid(h), dim3(kOrderBlock), 0, &o);
+        if (st != AG_OK) { hipGraphDestroy(g); return st; }
+        prev = node;
+        a.perm = h->perm;
+    }
     for (int done = 0; done < n_steps; done += k) {
         a.t_off = done;
         a.k = std::min(k, n_steps - done);
@@ -516,6 +547,7 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
     h->d_step = reinterpret_cast<long long*>(h->ws + L.d_step);
     h->acc = reinterpret_cast<StatAcc*>(h->ws + L.acc);
     h->slots = reinterpret_cast<StatSlot*>(h->ws + L.slots);
+    h->perm = reinterpret_cast<int32_t*>(h->ws + L.perm);
     h->block_counts = reinterpret_cast<int32_t*>(h->ws + L.block_counts);
     h->mask_buf = reinterpret_cast<uint8_t*>(h->ws + L.mask);
     h->scratch = cfg->autotune_scratch ? reinterpret_cast<float*>(h->ws + L.scratch) : nullptr;
@@ -718,7 +750,7 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     int occ_blocks_per_cu = 0;
     const int blocks[] = {64, 128, 256, 512};
     const int vpls[] = {1, 2};
-    const int ks[] = {4, 8, 16, 32, 64, 128, 256, 512};
+    const int ks[] = {4, 8, 16, 32, 64, 128, 256, 512, 1024};
     ag_exec best = h->exec;
     float best_ms = 1e30f;
     const long long saved_t = h->t;

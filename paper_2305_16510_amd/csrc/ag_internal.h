@@ -69,6 +69,7 @@ struct StepArgs {
     uint32_t index_base;
     float lo[3], hi[3];
     EvBufs ev;                 // reset events (RESET kernels)
+    const int32_t* perm;       // [n] vehicle of each lane position (fused kernels), or null: identity
 };
 
 struct ResetArgs {
@@ -226,5 +227,24 @@ const void* ev_mask_kernel();
 const void* ev_scan_kernel();
 const void* ev_scatter_kernel();
 const void* ev_redraw_kernel();
+
+// Mode order of a fused launch: in every segment of kOrderSeg consecutive
+// vehicles, the vehicles of each group are listed stably by command mode
+// (0, 1, 2, then every other code), so that wavefronts hold one mode; each
+// vehicle stays in its segment and its group.  A segment split by more than
+// kOrderPieces groups is listed in index order.
+constexpr int kOrderSeg = 4096;
+constexpr int kOrderPieces = 8;
+constexpr int kOrderBlock = 256;
+// fused launches of at least this many steps per call use the order
+constexpr int kOrderMinSteps = 32;
+struct OrderArgs {
+    const int8_t* mode;
+    const int32_t* goff;
+    int32_t* perm;
+    long long n;
+    int32_t n_groups;
+};
+const void* mode_order_kernel();
 
 }  // namespace ag

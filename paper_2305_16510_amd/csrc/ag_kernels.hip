@@ -99,6 +99,10 @@ __device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, l
     }
 }
 
+constexpr bool spec_loops(bool one, int vpl, bool obs, bool trk, int rst) {
+    return !one && vpl == 1 && !obs && !trk && rst == 0;
+}
+
 // The tiles of one block.  UNI (per-step kernels of a single-group launch):
 // the one group entry is loaded ahead of the state and written to LDS
 // without the group search and its extra barrier.
@@ -110,6 +114,10 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
     constexpr bool RESET = RST != 0;
     constexpr bool EV = RESET && !ONE;
     constexpr bool FB = !(EV && RST == 2);
+    // fused one-vehicle-per-lane kernels without observers, trajectories or
+    // resets carry mode-specialised copies of the step loop (the other forms
+    // would exceed 128 registers with them)
+    constexpr bool SPEC = spec_loops(ONE, VPL, OBS, TRK, RST);
     const int B = blockDim.x;
     const long long TILE = (long long)B * VPL;
     const long long tbase = a.d_step ? (*a.d_step + a.t_off) : a.t0;
@@ -152,12 +160,17 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         // n load vehicle n - 1 and discard it
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
-            const long long i = base + (long long)v * B + threadIdx.x;
-            idx[v] = i;
-            act[v] = i < a.n;
+            const long long p = base + (long long)v * B + threadIdx.x;
+            act[v] = p < a.n;
             sat_last[v] = 0;
             did_reset[v] = false;
-            const long long il = act[v] ? i : a.n - 1;
+            const long long pl = act[v] ? p : a.n - 1;
+            // with a mode order, lane position p steps vehicle perm[p] (same
+            // group as vehicle p, so the staged table entries still apply)
+            const long long il = (SPEC && a.perm) ? (long long)a.perm[pl] : pl;
+            // (the other kernels store through the unclamped position, so the
+            // compiler does not keep the load addresses live for the stores)
+            idx[v] = SPEC ? il : p;
 #pragma unroll
             for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + il];
             md[v] = (int)a.mode[il];
@@ -206,8 +219,9 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         // one step of every lane; OUT: the step that writes the wrench and rotor
         // outputs (the launch's last), peeled off the loop so that the loop
         // does not carry its registers
-        auto run_step = [&](const int st, auto out_tag) {
+        auto run_step = [&](const int st, auto out_tag, auto ms_tag) {
             constexpr bool OUT = decltype(out_tag)::value;
+            constexpr int MS = decltype(ms_tag)::value;
             if constexpr (RESET && ONE) {
                 // reset words of four consecutive steps come from one Philox call
                 const long long tb = (tbase + st) >> 2;
@@ -255,7 +269,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                 }
                 int ns;
                 if constexpr (OUT) ns = step<NR, true, true, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, &W[v], u[v]);
-                else ns = step<NR, false, false, TRK>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
+                else ns = step<NR, false, false, TRK, MS>(s[v], C[v], P[v], gt[v], a.dt, a.g, nullptr, nullptr);
                 if constexpr (OBS) {
                     c_sat += ns;
                     sat_last[v] = ns;
@@ -263,13 +277,33 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             }
         };
         const int k_loop = want_out ? K - 1 : K;
-        for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{});
-        if (want_out) run_step(K - 1, std::true_type{});
+        using General = std::integral_constant<int, -1>;
+        auto run_loop = [&](auto ms_tag) {
+            for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{}, ms_tag);
+        };
+        if constexpr (SPEC) {
+            const int m_first = __builtin_amdgcn_readfirstlane(md[0]);
+            const int wm = __all(md[0] == m_first) ? m_first : -1;
+            switch (wm) {
+            case 0: run_loop(std::integral_constant<int, 0>{}); break;
+            case 1: run_loop(std::integral_constant<int, 1>{}); break;
+            case 2: run_loop(std::integral_constant<int, 2>{}); break;
+            default: run_loop(General{}); break;
+            }
+        } else {
+            // (the plain loop, not run_loop: the per-step kernels compile to
+            // fewer registers this way)
+            for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{}, General{});
+        }
+        if (want_out) run_step(K - 1, std::true_type{}, General{});
 
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
             if (!act[v]) continue;
-            const long long i = idx[v];
+            long long i = idx[v];
+            // the store addresses are formed here, not kept from the loads
+            // across the step loop (they would hold 26 registers)
+            if constexpr (SPEC) asm volatile("" : "+v"(i));
 #pragma unroll
             for (int r = 0; r < 13; ++r) a.state[r * ld + i] = s[v][r];
             if constexpr (RESET) {
@@ -336,7 +370,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
 }
 
 template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RST == 2 && VPL == 1 ? 4 : 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VPL == 1 && (RST == 2 || spec_loops(ONE, VPL, OBS, TRK, RST)) ? 4 : 1)))
 void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
@@ -538,6 +572,107 @@ __global__ __launch_bounds__(kResetBlock) void k_ev_mask(StepArgs a) {
 // block, fixed order, 64-bit: totals may exceed 2^31).  Each thread sums a
 // contiguous run of counts, one block-wide scan combines the runs, and each
 // thread writes its run's offsets.
+// ---- mode order of fused launches -------------------------------------------
+// One block per segment of kOrderSeg vehicles.  Each piece of the segment that
+// lies in one group is partitioned stably by mode bucket (0, 1, 2, other):
+// every thread counts its 16 consecutive vehicles per bucket, a block-wide
+// exclusive scan of the four counts (16-bit fields of one 64-bit word, each at
+// most kOrderSeg) gives its offsets, and it writes its vehicles there in index
+// order.
+__global__ __launch_bounds__(kOrderBlock) void k_mode_order(OrderArgs a) {
+    constexpr int PER = kOrderSeg / kOrderBlock;
+    constexpr int NW = kOrderBlock / 64;
+    __shared__ long long cut[kOrderPieces + 1];
+    __shared__ int ncut;
+    __shared__ unsigned long long wsum[NW];
+    const long long base = (long long)blockIdx.x * kOrderSeg;
+    const long long end = base + kOrderSeg < a.n ? base + kOrderSeg : a.n;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    if (t == 0) {
+        // piece boundaries: the group ends inside the segment
+        int g = a.n_groups == 1 ? 0 : find_group(a.goff, a.n_groups, base);
+        int c = 0;
+        cut[c++] = base;
+        for (;;) {
+            const long long nxt = a.goff[g + 1];
+            if (nxt >= end) {
+                cut[c++] = end;
+                break;
+            }
+            if (c == kOrderPieces) {
+                c = -1;
+                break;
+            }
+            cut[c++] = nxt;
+            ++g;
+        }
+        ncut = c;
+    }
+    __syncthreads();
+    const int nc = ncut;
+    if (nc < 0) {
+        for (int j = 0; j < PER; ++j) {
+            const long long q = base + (long long)t * PER + j;
+            if (q < end) a.perm[q] = (int32_t)q;
+        }
+        return;
+    }
+    for (int c = 0; c + 1 < nc; ++c) {
+        const long long p0 = cut[c], p1 = cut[c + 1];
+        const long long q0 = p0 + (long long)t * PER;
+        int bk[PER];
+        unsigned long long cnt = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const long long q = q0 + j;
+            bk[j] = -1;
+            if (q < p1) {
+                const int m = a.mode[q];
+                bk[j] = (m >= 0 && m <= 2) ? m : 3;
+                cnt += 1ull << (16 * bk[j]);
+            }
+        }
+        unsigned long long inc = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        unsigned long long pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            if (w < wid) pre += wsum[w];
+            tot += wsum[w];
+        }
+        const unsigned long long excl = pre + inc - cnt;
+        long long at[4];
+        long long start = p0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            at[b] = start + (long long)((excl >> (16 * b)) & 0xffffull);
+            start += (long long)((tot >> (16 * b)) & 0xffffull);
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int b = bk[j];
+            if (b >= 0) {
+                long long pos = at[0];
+                if (b == 1) pos = at[1];
+                if (b == 2) pos = at[2];
+                if (b == 3) pos = at[3];
+                a.perm[pos] = (int32_t)(q0 + j);
+                if (b == 0) ++at[0];
+                if (b == 1) ++at[1];
+                if (b == 2) ++at[2];
+                if (b == 3) ++at[3];
+            }
+        }
+        __syncthreads();   // wsum is reused by the next piece
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
     __shared__ long long buf[1024];
     const int nblocks = (int)((a.n + kResetBlock - 1) / kResetBlock);
@@ -751,5 +886,6 @@ const void* ev_mask_kernel() { return reinterpret_cast<const void*>(&k_ev_mask);
 const void* ev_scan_kernel() { return reinterpret_cast<const void*>(&k_ev_scan); }
 const void* ev_scatter_kernel() { return reinterpret_cast<const void*>(&k_ev_scatter); }
 const void* ev_redraw_kernel() { return reinterpret_cast<const void*>(&k_ev_redraw); }
+const void* mode_order_kernel() { return reinterpret_cast<const void*>(&k_mode_order); }
 
 }  // namespace ag

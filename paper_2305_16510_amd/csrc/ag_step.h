@@ -208,7 +208,7 @@ struct Adj {
 // which is then pulled back through integration, allocation (clamp
 // subgradient 1 inside [u_min, u_max], bounds included), the moment law,
 // the tilt extraction, the yaw readout and R(q).
-template <int NRC, bool WANT_W, bool WANT_U, bool GRAD, bool TRK = false>
+template <int NRC, bool WANT_W, bool WANT_U, bool GRAD, bool TRK = false, int MS = -1>
 AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
                      float dt, float g, Wrench* W, float* u_out, Adj* adj) {
     constexpr int NR = RotorClass<NRC>::NR;
@@ -233,7 +233,13 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float cpsi = (R00 + kTiny) * ir;
     const float spsi = R10 * ir;
 
-    const int mode = C.mode;
+    // MS >= 0: every vehicle of the call has mode MS (the selects below fold
+    // to one side; the arithmetic of the remaining side is unchanged).  Every
+    // mode select is a statement of its own, never an operand inside a longer
+    // expression: multiply-adds are contracted per expression from the form
+    // of its operands, so a select that folds to a product would otherwise
+    // contract differently in a specialised copy.
+    const int mode = MS >= 0 ? MS : C.mode;
     const bool m0 = mode == 0, m1 = mode == 1, m2 = mode == 2, m3 = mode == 3;
 
     // ---- reference yaw frame: psi_d (position) or current psi -------------
@@ -255,7 +261,8 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float kvm_xy = P.m * P.kv_xy, kvm_z = P.m * P.kv_z;
     const float Kx = kxm_xy * C.t0, Ky = kxm_xy * C.t1;
     const float Vx = m1 ? kvm_xy * C.t0 : 0.0f, Vy = m1 ? kvm_xy * C.t1 : 0.0f;
-    const float Kz = kxm_z * C.t2 + ((m1 ? kvm_z * C.t2 : 0.0f) + P.m * g);
+    const float Vz = m1 ? kvm_z * C.t2 : 0.0f;
+    const float Kz = kxm_z * C.t2 + (Vz + P.m * g);
     const float Ax = Kx - kxm_xy * s[0] - kvm_xy * vx;
     const float Ay = Ky - kxm_xy * s[1] - kvm_xy * vy;
     const float Fx = cr * Ax + (sr * Ay + Vx);
@@ -715,10 +722,10 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     return nsat;
 }
 
-template <int NRC, bool WANT_W, bool WANT_U, bool TRK = false>
+template <int NRC, bool WANT_W, bool WANT_U, bool TRK = false, int MS = -1>
 AG_DEV int step(float (&s)[13], const Cmd& C, const Params& P, const float* __restrict__ gt,
                 float dt, float g, Wrench* W, float* u_out) {
-    return step_core<NRC, WANT_W, WANT_U, false, TRK>(s, C, P, gt, dt, g, W, u_out, nullptr);
+    return step_core<NRC, WANT_W, WANT_U, false, TRK, MS>(s, C, P, gt, dt, g, W, u_out, nullptr);
 }
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) ---------------------------------
