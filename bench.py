@@ -22,9 +22,23 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic work per vehicle-step: bytes of the per-step
 # kernel (state in and out, 4-float command, mode byte) and FP32 flops of one
-# step on the shared straight-line path (quad allocation).
+# quad step per command mode, counted operation by operation on that mode's
+# path (an FMA as two, a reciprocal square root as one, per-vehicle constants
+# hoisted, products with structural zeros and the 2^-60 biases excluded):
+# position 215, velocity 221, attitude 188, wrench or unknown code 117.
 BYTES_PER_VSTEP = 52 + 52 + 16 + 1
-FLOPS_PER_VSTEP = 274
+FLOPS_BY_MODE = {0: 215, 1: 221, 2: 188}
+FLOPS_OTHER_MODE = 117
+
+
+def flops_per_vstep(mode):
+    """Mean algorithmic flops per vehicle-step over a fleet's modes."""
+    import numpy as np
+    m = np.asarray(mode).astype(np.int64)
+    f = np.full(m.shape, float(FLOPS_OTHER_MODE))
+    for code, fl in FLOPS_BY_MODE.items():
+        f[m == code] = fl
+    return float(f.mean())
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the
@@ -33,10 +47,10 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "a6856f3e7768236c",
-    "per_step_bytes": 126996212.1,
-    "fused_bytes": 126991059.7,
-    "fused_valu_per_vstep": 187.1,
+    "src": "5edc4495f7fd33db",
+    "per_step_bytes": 128051320.7,
+    "fused_bytes": 384698343.3,
+    "fused_valu_per_vstep": 146.0,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
@@ -269,7 +283,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=1024)
     ap.add_argument("--n", type=int, default=1_048_576)
     ap.add_argument("--probe-steps", type=int, default=1024,
                     help="steps per autotuning trial (also the largest k tried)")
@@ -381,7 +395,8 @@ def main():
 
     # achieved = algorithmic flops of the timed launches / their event time
     # (the last launch of a K that k does not divide runs fewer steps)
-    tflops = FLOPS_PER_VSTEP * wl.n * K / t_evt["fused"] / 1e12
+    fl_vstep = flops_per_vstep(wl.mode)
+    tflops = fl_vstep * wl.n * K / t_evt["fused"] / 1e12
     valid = counters_valid()
     # VALU utilisation: lane-instructions issued per second against the chip's
     # peak issue rate (157.3 TFLOP/s = 78.6e12 single-lane FMAs per second)
@@ -409,7 +424,7 @@ def main():
                      # one load and one store of the state per launch, whatever k
                      "traffic": COUNTERS["fused_bytes"] if valid else None,
                      "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
-                     "steps_per_launch": k, "flops_per_vehicle_step": FLOPS_PER_VSTEP,
+                     "steps_per_launch": k, "flops_per_vehicle_step": fl_vstep,
                      "valu_instr_per_vehicle_step": COUNTERS["fused_valu_per_vstep"] if valid else None,
                      "valu_issue_frac_of_peak": valu_util,
                      "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},

@@ -312,7 +312,9 @@ bool uses_events(ag_handle h, const ag_exec& e) { return h->reset_on && e.kind =
 // (their kernels have the mode-specialised step loops; the order costs one
 // pass over the modes per call, so short calls go without it).
 bool uses_order(ag_handle h, const ag_exec& e, int n_steps) {
-    return e.kind == 1 && e.vpl == 1 && h->cfg.traj == nullptr && n_steps >= kOrderMinSteps;
+    const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
+    return e.kind == 1 && e.vpl == 1 && h->cfg.traj == nullptr && !obs && !h->reset_on &&
+           n_steps >= kOrderMinSteps;
 }
 
 OrderArgs order_args(ag_handle h) {
