@@ -18,6 +18,8 @@
 // in the issue slots it leaves idle.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ag.h"
 #include "ag_internal.h"
 #include "ag_step.h"
@@ -65,6 +67,25 @@ __device__ __forceinline__ void copy_entry(EntryRegs& g, const float* gt) {
     for (int k = 0; k < GSTRIDE; ++k) g.e[k] = gt[k];
 }
 
+// The mode shared by every active lane of the wavefront if it is 0, 1 or 2
+// (the step then runs that mode's specialised copy), else -1.
+__device__ __forceinline__ int wave_mode(int mode) {
+    const int mf = __builtin_amdgcn_readfirstlane(mode);
+    return (__all(mode == mf) && mf >= 0 && mf <= 2) ? mf : -1;
+}
+
+// Call fn with std::integral_constant<int, wm> for wm in -1..2 (wm uniform
+// across the wavefront).
+template <typename F>
+__device__ __forceinline__ void by_mode(int wm, F&& fn) {
+    switch (wm) {
+    case 0: fn(std::integral_constant<int, 0>{}); break;
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    default: fn(std::integral_constant<int, -1>{}); break;
+    }
+}
+
 template <int NR>
 __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     extern __shared__ float4 lds4[];
@@ -88,17 +109,20 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
     const float gx = C.t0, gy = C.t1, gz = C.t2;
     double loss = 0.0;
-    for (int t = 0; t < a.T; ++t) {
-        if (t % a.m == 0) {
-            float* ck = a.ckpt + (long long)(t / a.m) * 13 * n;
+    by_mode(wave_mode(C.mode), [&](auto ms) {
+        constexpr int MS = decltype(ms)::value;
+        for (int t = 0; t < a.T; ++t) {
+            if (t % a.m == 0) {
+                float* ck = a.ckpt + (long long)(t / a.m) * 13 * n;
 #pragma unroll
-            for (int r = 0; r < 13; ++r) ck[r * n + i] = s[r];
+                for (int r = 0; r < 13; ++r) ck[r * n + i] = s[r];
+            }
+            step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+            const float ex = s[0] - gx, ey = s[1] - gy, ez = s[2] - gz;
+            const float lt = ex * ex + ey * ey + ez * ez + a.w_omega * (s[10] * s[10] + s[11] * s[11] + s[12] * s[12]);
+            loss += (double)lt;
         }
-        step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
-        const float ex = s[0] - gx, ey = s[1] - gy, ez = s[2] - gz;
-        const float lt = ex * ex + ey * ey + ez * ez + a.w_omega * (s[10] * s[10] + s[11] * s[11] + s[12] * s[12]);
-        loss += (double)lt;
-    }
+    });
     if (a.loss_out) a.loss_out[i] = (float)loss;
     if (a.final_state) {
 #pragma unroll
@@ -107,7 +131,7 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
 }
 
 // Recompute segment seg from its checkpoint: tape entry t - t0 = state before step t.
-template <int NR>
+template <int NR, int MS>
 __device__ __forceinline__ void recompute_segment(const RolloutArgs& a, const Params& P, const Cmd& C,
                                                   const float* gt, int seg, float* tape, long long i) {
     const long long n = a.n;
@@ -121,13 +145,13 @@ __device__ __forceinline__ void recompute_segment(const RolloutArgs& a, const Pa
         float* tp = tape + (long long)(t - t0) * 13 * n;
 #pragma unroll
         for (int r = 0; r < 13; ++r) tp[r * n + i] = s[r];
-        if (t + 1 < t1) step<NR, false, false>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+        if (t + 1 < t1) step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
     }
 }
 
 // Reverse sweep of segment seg over its tape; the next (earlier) tape entry is
 // loaded while the current step's reverse runs, hiding the load latency.
-template <int NR>
+template <int NR, int MS>
 __device__ __forceinline__ void reverse_segment(const RolloutArgs& a, const Params& P, const Cmd& C,
                                                 const float* gt, int seg, const float* tape, long long i, Adj& A) {
     const long long n = a.n;
@@ -147,7 +171,7 @@ __device__ __forceinline__ void reverse_segment(const RolloutArgs& a, const Para
 #pragma unroll
             for (int r = 0; r < 13; ++r) nxt[r] = tp[r * n + i];
         }
-        step_core<NR, false, false, true>(s, C, P, gt, a.dt, a.g, nullptr, nullptr, &A);
+        step_core<NR, false, false, true, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr, &A);
     }
 }
 
@@ -176,7 +200,13 @@ __global__ __launch_bounds__(128) void k_rollout_adj(RolloutArgs a) {
         derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
     }
     const int last = a.n_ckpt - 1;
-    if (!reverse_wave && act) recompute_segment<NR>(a, P, C, gt, last, a.tape + (last & 1) * buf, i);
+    // every step of this wavefront runs its mode's specialised copy when its
+    // vehicles share a mode
+    const int wm = wave_mode(C.mode);
+    if (!reverse_wave && act)
+        by_mode(wm, [&](auto ms) {
+            recompute_segment<NR, decltype(ms)::value>(a, P, C, gt, last, a.tape + (last & 1) * buf, i);
+        });
     __syncthreads();
     Adj A;
 #pragma unroll
@@ -187,9 +217,14 @@ __global__ __launch_bounds__(128) void k_rollout_adj(RolloutArgs a) {
     A.w_omega = a.w_omega;
     for (int seg = last; seg >= 0; --seg) {
         if (reverse_wave) {
-            if (act) reverse_segment<NR>(a, P, C, gt, seg, a.tape + (seg & 1) * buf, i, A);
+            if (act)
+                by_mode(wm, [&](auto ms) {
+                    reverse_segment<NR, decltype(ms)::value>(a, P, C, gt, seg, a.tape + (seg & 1) * buf, i, A);
+                });
         } else if (seg > 0 && act) {
-            recompute_segment<NR>(a, P, C, gt, seg - 1, a.tape + ((seg - 1) & 1) * buf, i);
+            by_mode(wm, [&](auto ms) {
+                recompute_segment<NR, decltype(ms)::value>(a, P, C, gt, seg - 1, a.tape + ((seg - 1) & 1) * buf, i);
+            });
         }
         __syncthreads();
     }
