@@ -47,10 +47,10 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "5edc4495f7fd33db",
-    "per_step_bytes": 128051320.7,
-    "fused_bytes": 384698343.3,
-    "fused_valu_per_vstep": 146.0,
+    "src": "5bdd03f4d4424483",
+    "per_step_bytes": 127013218.0,
+    "fused_bytes": 416777588.8,
+    "fused_valu_per_vstep": 143.8,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",

@@ -263,11 +263,16 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     const float Vx = m1 ? kvm_xy * C.t0 : 0.0f, Vy = m1 ? kvm_xy * C.t1 : 0.0f;
     const float Vz = m1 ? kvm_z * C.t2 : 0.0f;
     const float Kz = kxm_z * C.t2 + (Vz + P.m * g);
-    const float Ax = Kx - kxm_xy * s[0] - kvm_xy * vx;
-    const float Ay = Ky - kxm_xy * s[1] - kvm_xy * vy;
+    // the position terms are selects of their own (zero outside position
+    // mode), so a velocity-mode copy of the step drops them
+    const float Qx = m0 ? Kx - kxm_xy * s[0] : 0.0f;
+    const float Qy = m0 ? Ky - kxm_xy * s[1] : 0.0f;
+    const float Ax = Qx - kvm_xy * vx;
+    const float Ay = Qy - kvm_xy * vy;
     const float Fx = cr * Ax + (sr * Ay + Vx);
     const float Fy = cr * Ay + (Vy - sr * Ax);
-    const float Fz = Kz - kxm_z * s[2] - kvm_z * vz;
+    const float Qz = m0 ? Kz - kxm_z * s[2] : Kz;
+    const float Fz = Qz - kvm_z * vz;
     // the same quantities in the plain decomposition (reverse pass only)
     const float vVx = cr * vx + sr * vy;
     const float vVy = cr * vy - sr * vx;
@@ -316,9 +321,10 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
     // ---- e_Omega = Omega - psidot_d R^T e3 ---------------------------------
     const float psidot = m1 ? C.t3 : (m2 ? C.t2 : 0.0f);
     const float w0 = s[10], w1 = s[11], w2 = s[12];
-    float eW0 = w0 - psidot * R20;
-    float eW1 = w1 - psidot * R21;
-    float eW2 = w2 - psidot * R22;
+    // (psidot_d = 0 in position mode: e_Omega = Omega)
+    float eW0 = m0 ? w0 : w0 - psidot * R20;
+    float eW1 = m0 ? w1 : w1 - psidot * R21;
+    float eW2 = m0 ? w2 : w2 - psidot * R22;
 
     // ---- gyroscopic term Omega x J Omega ------------------------------------
     // for diagonal J its components are (J2 - J1) w1 w2, (J0 - J2) w2 w0 and
