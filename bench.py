@@ -47,10 +47,10 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "5bdd03f4d4424483",
-    "per_step_bytes": 127013218.0,
-    "fused_bytes": 416777588.8,
-    "fused_valu_per_vstep": 143.8,
+    "src": "e8afde36819affc5",
+    "per_step_bytes": 126997679.9,
+    "fused_bytes": 134106477.9,
+    "fused_valu_per_vstep": 143.3,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",

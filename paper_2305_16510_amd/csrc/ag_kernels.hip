@@ -362,7 +362,19 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         if (base < a.n) tile_body(base);
     } else {
         const long long ntiles = (a.n + TILE - 1) / TILE;
-        for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile * TILE);
+        if (SPEC && NR != 0 && a.perm && (long long)gridDim.x == ntiles) {
+            // In mode order, the three mode runs of a segment read the same
+            // cache lines (each wavefront gathers its 64 vehicles from about
+            // 192 positions).  Blocks are dealt to the 8 XCDs in turn (block i
+            // to XCD i mod 8); giving each XCD a contiguous eighth of the
+            // tiles lets those runs meet in one L2.  (Not for launches mixing
+            // rotor counts: their groups would load the XCDs unevenly.)
+            const long long i = blockIdx.x, x = i & 7, j = i >> 3;
+            const long long per = ntiles >> 3, rem = ntiles & 7;
+            tile_body((x * per + (x < rem ? x : rem) + j) * TILE);
+        } else {
+            for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile * TILE);
+        }
     }
     if constexpr (OBS) {
         if (a.slots) block_stats(a.slots, c_sat, c_res, c_nonf, c_fin, c_pos, s_err, s_w);
