@@ -47,9 +47,9 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "e8afde36819affc5",
-    "per_step_bytes": 126997679.9,
-    "fused_bytes": 134106477.9,
+    "src": "86a3d4ff62ae5a42",
+    "per_step_bytes": 127014519.5,
+    "fused_bytes": 134596098.3,
     "fused_valu_per_vstep": 143.3,
     "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
 }

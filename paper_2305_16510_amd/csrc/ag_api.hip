@@ -174,9 +174,14 @@ bool build_group_entry(const ag_group_desc& g, float* e) {
     for (int i = 0; i < n; ++i) {
         const double al = pi / n + 2.0 * pi * i / n;
         const double s = (i % 2 == 0) ? 1.0 : -1.0;
+        // sines and cosines that are zero in exact arithmetic (cos of 90 and
+        // 270 degrees) come out of the library as ~1e-16: take them as zero
+        double sa = std::sin(al), ca = std::cos(al);
+        if (std::fabs(sa) < 1e-12) sa = 0.0;
+        if (std::fabs(ca) < 1e-12) ca = 0.0;
         A[0][i] = 1.0;
-        A[1][i] = std::sin(al);
-        A[2][i] = -std::cos(al);
+        A[1][i] = sa;
+        A[2][i] = -ca;
         A[3][i] = s * (double)g.c_tau;
     }
     double G[4][4] = {}, Gi[4][4];
@@ -189,6 +194,9 @@ bool build_group_entry(const ag_group_desc& g, float* e) {
         for (int r = 0; r < 4; ++r) {
             double p = 0.0;
             for (int c = 0; c < 4; ++c) p += A[c][i] * Gi[c][r];
+            // (entries that vanish in exact arithmetic come out of the FP64
+            // inverse as ~1e-17; every other entry is at least ~0.1)
+            if (std::fabs(p) < 1e-12) p = 0.0;
             e[G_APINV + 4 * i + r] = (float)p;
             e[G_ACOL + 4 * i + r] = (float)A[r][i];
         }
@@ -223,6 +231,23 @@ bool build_group_entry(const ag_group_desc& g, float* e) {
         e[G_Q_Z] = p0[3];
         e[G_Q_S] = c0[1];
         e[G_Q_CT] = c0[3];
+    } else {
+        // hexa and octo: the kernels' pair form assumes that rotor i + n/2
+        // has rotor i's rows with the x-y terms negated and the yaw term
+        // times (-1)^(n/2), and that the yaw terms alternate in sign
+        const int h = n / 2;
+        const float so = (h % 2) ? -1.0f : 1.0f;
+        for (int k = 0; k < 2; ++k) {
+            const float* t = e + (k == 0 ? G_APINV : G_ACOL);
+            for (int i = 0; i < n; ++i) {
+                const float* r = t + 4 * i;
+                if (r[0] != t[0] || r[3] != ((i % 2) ? -t[3] : t[3])) return false;
+                if (i < h) {
+                    const float* o = t + 4 * (i + h);
+                    if (o[1] != -r[1] || o[2] != -r[2] || o[3] != so * r[3]) return false;
+                }
+            }
+        }
     }
     return true;
 }

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #ifndef AG_DEV
 #define AG_DEV __device__ __forceinline__
 #endif
@@ -446,41 +448,59 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         k01 = P.armq;
         k2 = P.ctq;
     };
-    // any layout: u = clip(A1^+ (f, M_x/l, M_y/l, M_z)), X = A1 u (rows 1..3)
-    auto table_alloc = [&]() {
+    // Hexa and octo: rotor i + n/2 sits opposite rotor i (angle + pi), so its
+    // row of A1^+ (and of A1) has the x-y terms negated and the yaw term
+    // times (-1)^(n/2).  With L_i the x-y part of rotor i's row, rotor i
+    // takes c_f f + s_i Z + L_i and rotor i + n/2 takes c_f f + s_(i+n/2) Z
+    // - L_i; the applied sums run over the pair differences and sums, the
+    // yaw sum without c_tau (applied as k2).
+    auto pair_alloc = [&](auto n_tag) {
+        constexpr int N = decltype(n_tag)::value, H = N / 2;
+        const float4 p0 = *reinterpret_cast<const float4*>(gt + G_APINV);
+        const float4 c0 = *reinterpret_cast<const float4*>(gt + G_ACOL);
+        const float cf = p0.x * f, zs = p0.w * Ms2;
+        const float cp = cf + zs, cm = cf - zs;      // spin + and spin - rotors
+        float yaw = 0.0f;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            // in a mixed launch, lanes with fewer rotors skip slots 4..7 (every
-            // layout has at least 4); a wavefront inside one group skips them
-            // entirely, and a skipped slot leaves the sums as a zero thrust would
-            if (MIXED && r >= 4 && r >= P.nr) continue;
-            const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * r);
-            const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * r);
-            const float u = clamp_rotor(r, ap.x * f + ap.y * Ms0 + ap.z * Ms1 + ap.w * Ms2);
-            if (r == 0) {
-                fa = u * ac.x;
-                X0 = u * ac.y;
-                X1 = u * ac.z;
-                X2 = u * ac.w;
+        for (int i = 0; i < H; ++i) {
+            const float4 ap = *reinterpret_cast<const float4*>(gt + G_APINV + 4 * i);
+            const float4 ac = *reinterpret_cast<const float4*>(gt + G_ACOL + 4 * i);
+            const float L = ap.y * Ms0 + ap.z * Ms1;
+            const bool sp = (i & 1) == 0;                       // spin of rotor i
+            const bool so = (H & 1) ? !sp : sp;                 // spin of rotor i + H
+            const float ui = clamp_rotor(i, (sp ? cp : cm) + L);
+            const float uo = clamp_rotor(i + H, (so ? cp : cm) - L);
+            const float d = ui - uo, sm = ui + uo;
+            const float ys = (H & 1) ? d : sm;                  // yaw: s_i (u_i -+ u_o)
+            if (i == 0) {
+                fa = sm;
+                X0 = ac.y * d;
+                X1 = ac.z * d;
+                yaw = ys;
             } else {
-                fa += u * ac.x;
-                X0 += u * ac.y;
-                X1 += u * ac.z;
-                X2 += u * ac.w;
+                fa += sm;
+                X0 += ac.y * d;
+                X1 += ac.z * d;
+                yaw = sp ? yaw + ys : yaw - ys;
             }
         }
+        X2 = yaw;
         k01 = P.arm;
-        k2 = 1.0f;
+        k2 = c0.w;
     };
-    // every kernel that meets a quad takes the butterflies, so a quad group
-    // rounds identically in a quad-only and in a mixed launch
+    // every kernel that meets a quad takes the butterflies, and hexa and
+    // octo the pairs, so a group rounds identically in a launch of its own
+    // layout and in a mixed launch
     if constexpr (NRC == 4) {
         quad_alloc();
-    } else if constexpr (MIXED) {
-        if (P.nr == 4) quad_alloc();
-        else table_alloc();
+    } else if constexpr (NRC == 6) {
+        pair_alloc(std::integral_constant<int, 6>{});
+    } else if constexpr (NRC == 8) {
+        pair_alloc(std::integral_constant<int, 8>{});
     } else {
-        table_alloc();
+        if (P.nr == 4) quad_alloc();
+        else if (P.nr == 6) pair_alloc(std::integral_constant<int, 6>{});
+        else pair_alloc(std::integral_constant<int, 8>{});
     }
     if constexpr (WANT_W) {
         // the commanded moment in N m (the same law, unscaled)
@@ -573,7 +593,8 @@ AG_DEV int step_core(float (&s)[13], const Cmd& C, const Params& P, const float*
         // adjoint of the applied wrench's sums X, then of the raw thrusts
         // (clamp subgradient), then of (f, M): the transposes of the forward
         // products, as butterflies for the quad
-        const float bX0 = k01 * bMa0, bX1 = k01 * bMa1, bX2 = k2 * bMa2;
+        // (the table products below take the yaw sum with c_tau inside)
+        const float bX0 = k01 * bMa0, bX1 = k01 * bMa1, bX2 = quad ? k2 * bMa2 : bMa2;
         float bf, bM0, bM1, bM2;
         auto pass = [&](int r) { return (raws[r] >= P.umin) & (raws[r] <= P.umax); };
         auto quad_rev = [&]() {
