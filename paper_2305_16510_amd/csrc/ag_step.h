@@ -3,7 +3,9 @@
 // One lane owns one vehicle; everything here is straight-line FP32 scalar
 // code on registers (the 3x3 algebra is not a dense contraction, so no MFMA).
 // The three command modes share one branch-free path with selects, so a
-// wavefront holding a mix of modes never diverges.
+// wavefront holding a mix of modes never diverges; a caller whose wavefront
+// holds one mode instantiates step_core with that mode (MS), which folds the
+// selects and drops the work the mode does not need.
 //
 // The controller follows Sec. IV of Kulkarni et al. (arXiv 2305.16510) with
 // these algebraic rewrites, each exact in real arithmetic:
@@ -21,7 +23,8 @@
 //     constants, which a fused launch computes once (loop-invariant).
 // Allocation uses a unit-arm table per rotor layout: u = clip(A1^+ (f, M_x/l,
 // M_y/l, M_z)), applied wrench (sum u, l (A1 u)_1, l (A1 u)_2, (A1 u)_3);
-// for the quad X layout both products are 4-point butterflies.
+// for the quad X layout both products are 4-point butterflies, for hexa and
+// octo they run over opposite-rotor pairs.
 // Integration is semi-implicit Euler with quaternion renormalisation.
 #pragma once
 
