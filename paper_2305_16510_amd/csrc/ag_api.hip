@@ -190,13 +190,20 @@ bool build_group_entry(const ag_group_desc& g, float* e) {
             for (int i = 0; i < n; ++i) G[r][c] += A[r][i] * A[c][i];
     if (!invert4(G, Gi)) return false;
     for (int k = 0; k < GSTRIDE; ++k) e[k] = 0.0f;
+    double pinv[8][4], cmax[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < n; ++i) {
         for (int r = 0; r < 4; ++r) {
             double p = 0.0;
             for (int c = 0; c < 4; ++c) p += A[c][i] * Gi[c][r];
-            // (entries that vanish in exact arithmetic come out of the FP64
-            // inverse as ~1e-17; every other entry is at least ~0.1)
-            if (std::fabs(p) < 1e-12) p = 0.0;
+            pinv[i][r] = p;
+            cmax[r] = std::max(cmax[r], std::fabs(p));
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int r = 0; r < 4; ++r) {
+            // entries that vanish in exact arithmetic come out of the FP64
+            // inverse about 1e-16 times the column's largest entry
+            const double p = std::fabs(pinv[i][r]) < 1e-12 * cmax[r] ? 0.0 : pinv[i][r];
             e[G_APINV + 4 * i + r] = (float)p;
             e[G_ACOL + 4 * i + r] = (float)A[r][i];
         }
