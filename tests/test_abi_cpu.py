@@ -60,6 +60,9 @@ def test_workspace_size_grows_with_n_and_scratch(lib):
         assert b.value % 256 == 0
         sizes.append(b.value)
     assert sizes[0] < sizes[1] < sizes[2]
+    # per vehicle at least the mode order of fused calls (int32) and the
+    # reset mask (byte); the autotuning scratch holds state and commands
+    assert sizes[1] - sizes[0] >= 99_000 * (4 + 1)
     assert sizes[2] - sizes[1] >= 17 * 100_000 * 4
 
 
