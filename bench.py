@@ -47,7 +47,7 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "560eeec2902321d3",
+    "src": "03749f53ff77900e",
     "per_step_bytes": 127014519.5,
     "fused_bytes": 134596098.3,
     "fused_valu_per_vstep": 143.3,

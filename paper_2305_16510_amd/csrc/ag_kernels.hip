@@ -691,8 +691,20 @@ __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
     const int per = (nblocks + 1023) / 1024;
     const int b0 = (int)threadIdx.x * per;
     const int b1 = b0 + per < nblocks ? b0 + per : nblocks;
+    // a thread's run (up to RUN counts, 8.4 M vehicles) is loaded into
+    // registers at once, so its loads are in flight together; longer runs
+    // take the plain loop
+    constexpr int RUN = 32;
+    long long v[RUN];
     long long run = 0;
-    for (int j = b0; j < b1; ++j) run += a.ev.block_counts[j];
+    if (per <= RUN) {
+#pragma unroll
+        for (int j = 0; j < RUN; ++j) v[j] = b0 + j < b1 ? a.ev.block_counts[b0 + j] : 0;
+#pragma unroll
+        for (int j = 0; j < RUN; ++j) run += v[j];
+    } else {
+        for (int j = b0; j < b1; ++j) run += a.ev.block_counts[j];
+    }
     buf[threadIdx.x] = run;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -702,10 +714,18 @@ __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
         __syncthreads();
     }
     long long off = buf[threadIdx.x] - run;
-    for (int j = b0; j < b1; ++j) {
-        const long long c = a.ev.block_counts[j];
-        a.ev.block_counts[j] = off;
-        off += c;
+    if (per <= RUN) {
+#pragma unroll
+        for (int j = 0; j < RUN; ++j) {
+            if (b0 + j < b1) a.ev.block_counts[b0 + j] = off;
+            off += v[j];
+        }
+    } else {
+        for (int j = b0; j < b1; ++j) {
+            const long long c = a.ev.block_counts[j];
+            a.ev.block_counts[j] = off;
+            off += c;
+        }
     }
     if (threadIdx.x == 1023) *a.ev.total = buf[1023];
 }
