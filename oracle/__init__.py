@@ -19,8 +19,16 @@ allocation   rotor layout, min-norm allocation, clamping
 dynamics     rigid-body Newton-Euler and quaternion integration
 step         one step, rollouts, tracking loss, FP64 reverse-mode gradient, FD
 philox       Philox4x32-10 counter-based generator (Salmon et al., SC'11)
-reset        counter-based reset masks, redraws and ascending compaction
+reset        counter-based reset masks, redraws (Box-Muller normals) and ascending compaction
 stats        batch statistics
+task         goal-reaching observation, reward and termination (imported on its own)
+lee          full geometric tracking law with feed-forward (imported on its own)
+obstacles    obstacle poses at environment reset (imported on its own)
+raycast      depth images against primitive obstacles (imported on its own)
+
+Every function is pinned by a CPU test against a closed form, an identity, a
+hand-worked case or an independent implementation of a published definition,
+and a planted mistake in it makes that pin fail (``tests/test_oracle_*.py``).
 
 Parity status: the position-mode construction, the integrator, the rotor
 layout and the mass scaling of uneven fleets are readings (no paper numbers

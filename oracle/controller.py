@@ -40,6 +40,17 @@ def gain_vectors(gains):
     return kx, kv, gains[:, 4:7], gains[:, 7:10]
 
 
+def position_accel(kx, kv, x_d, x, v):
+    """Position mode (reading R8): a = kx o (x_d - x) - kv o v in the inertial
+    frame, with kx = (kx_xy, kx_xy, kx_z) and kv = (kv_xy, kv_xy, kv_z)."""
+    return kx * (x_d - x) - kv * v
+
+
+def velocity_accel(kv, v_d, v_V):
+    """Eq. (6): a_d = kv o (v_d - v), both in the vehicle frame V (R10)."""
+    return kv * (v_d - v_V)
+
+
 def tilt_from_force(F_V):
     """Eqs. (8)-(9) on the gravity-compensated force in V:
     phi_d = atan2(-F_y, sqrt(F_x^2 + F_z^2)), theta_d = atan2(F_x, F_z)."""
@@ -101,7 +112,7 @@ def control(x, v, q, Omega, mode, target, fleet, g, traj=None):
     # Position mode: a = kx (x_d - x) - kv v in E; F = m (a + g e3);
     # referenced to the commanded yaw psi_d with zero yaw rate.
     psi_d = target[:, 3]
-    a_E = kx * (target[:, :3] - x) - kv * v
+    a_E = position_accel(kx, kv, target[:, :3], x, v)
     F_E = m * (a_E + g * e3)
     RzT_d = rot_z(psi_d).transpose(-1, -2)
     F_V0 = mv(RzT_d, F_E)
@@ -110,7 +121,7 @@ def control(x, v, q, Omega, mode, target, fleet, g, traj=None):
     # Velocity mode: v expressed in V, eq. (6), eq. (7) read as a force.
     RzT = rot_z(psi).transpose(-1, -2)
     v_V = mv(RzT, v)
-    a_d = kv * (target[:, :3] - v_V)
+    a_d = velocity_accel(kv, target[:, :3], v_V)
     F_V1 = m * (a_d + g * e3)
     b3_V = mv(RzT, b3)
     f1 = (F_V1 * b3_V).sum(-1)

@@ -57,10 +57,18 @@ def draw_words(global_idx, t, seed):
     return np.concatenate(out, -1)          # [n, 16]
 
 
-def redraw(global_idx, t, seed, lo, hi):
-    """Fresh (state [n,13], goal [n,3]) in FP64 for the given vehicles."""
-    w = draw_words(global_idx, t, seed)
-    u = (w >> 8).astype(np.float64) * 2.0 ** -24
+def box_muller(ua, ub):
+    """Two independent standard normals from two independent uniforms on
+    [0, 1) (Box and Muller, 1958): radius sqrt(-2 ln(1 - ua)), angle 2 pi ub.
+    (1 - ua lies in (0, 1], so the logarithm is finite.)"""
+    r = np.sqrt(-2.0 * np.log(1.0 - ua))
+    return r * np.cos(2 * math.pi * ub), r * np.sin(2 * math.pi * ub)
+
+
+def state_from_uniforms(u, lo, hi):
+    """Fresh (state [n,13], goal [n,3]) in FP64 from 16 uniforms per vehicle
+    (u [n,16], the word layout of the module docstring)."""
+    u = np.asarray(u, np.float64)
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
     x = lo + (hi - lo) * u[:, 0:3]
@@ -76,13 +84,23 @@ def redraw(global_idx, t, seed, lo, hi):
     q = np.stack([a0 * b0, a0 * b1 - a3 * b2, a0 * b2 + a3 * b1, a3 * b0], -1)
     normals = []
     for a, b in ((9, 10), (11, 12), (13, 14)):
-        r = np.sqrt(-2.0 * np.log(1.0 - u[:, a]))
-        normals += [r * np.cos(2 * math.pi * u[:, b]), r * np.sin(2 * math.pi * u[:, b])]
+        normals += list(box_muller(u[:, a], u[:, b]))
     n = np.stack(normals, -1)
     v = VEL_SIGMA * n[:, 0:3]
     W = RATE_SIGMA * n[:, 3:6]
     s = np.concatenate([x, v, q, W], -1)
     return torch.as_tensor(s), torch.as_tensor(goal)
+
+
+def uniforms(global_idx, t, seed):
+    """The 16 uniforms u_k = (w_k >> 8) 2^-24 of each vehicle's redraw."""
+    w = draw_words(global_idx, t, seed)
+    return (w >> 8).astype(np.float64) * 2.0 ** -24
+
+
+def redraw(global_idx, t, seed, lo, hi):
+    """Fresh (state [n,13], goal [n,3]) in FP64 for the given vehicles."""
+    return state_from_uniforms(uniforms(global_idx, t, seed), lo, hi)
 
 
 def apply(state, mode, target, global_idx, t, seed, p, lo, hi, explicit_mask=None):

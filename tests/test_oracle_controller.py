@@ -220,3 +220,89 @@ def test_wrench_mode_and_unknown_mode():
     out7 = run(z, z, R, z, 7, tgt)
     assert torch.equal(out7["f"], torch.zeros(n, dtype=F64))
     assert torch.equal(out7["M"], torch.zeros(n, 3, dtype=F64))
+
+
+# ---- split gains (kx_xy != kx_z, kv_xy != kv_z) and nonzero velocity ---------
+# Every case below is level (b3 = e3) with zero body rate, so the commanded
+# force is the only thing that moves; values are exact in FP32, so the fleet
+# holds them unrounded.
+SPLIT_GAINS = (1.5, 3.0, 2.5, 0.75, 1.6, 1.6, 0.6, 0.5, 0.5, 0.2)
+SPLIT_MASS = 1.25
+
+
+def split_fleet(n):
+    from workloads import Group
+    return Fleet.from_groups([Group(0, n, mass=SPLIT_MASS, gains=SPLIT_GAINS)], n)
+
+
+def test_position_mode_vertical_velocity_is_damped_by_kv_z():
+    """Eq. (6) read for position mode (R8): at the goal, level, v = (0, 0, c):
+    a = -kv_z c e3, so F is vertical, f = m (g - kv_z c), the desired attitude
+    is the commanded yaw frame and M = 0."""
+    c = torch.tensor([2.0, -1.5, 0.5, 4.0], dtype=F64)
+    n = c.shape[0]
+    psi_d = torch.tensor([0.0, 0.7, -2.2, 3.0], dtype=F64)
+    xg = torch.tensor([[1.0, -2.0, 0.5]] * n, dtype=F64)
+    v = torch.zeros(n, 3, dtype=F64)
+    v[:, 2] = c
+    z = torch.zeros(n, 3, dtype=F64)
+    out = run(xg, v, so3.rot_z(psi_d), z, 0, torch.cat([xg, psi_d[:, None]], -1), split_fleet(n))
+    kv_z = SPLIT_GAINS[3]
+    assert (out["f"] - SPLIT_MASS * (G - kv_z * c)).abs().max() < 1e-13
+    assert out["M"].abs().max() < 1e-13
+    assert out["phi_d"].abs().max() < 1e-15 and out["theta_d"].abs().max() < 1e-15
+
+
+def test_position_mode_horizontal_velocity_tilts_against_it():
+    """Position mode at the goal with v = R_z(psi_d) (c, 0, 0):
+    F_V = m (-kv_xy c, 0, g), hence theta_d = atan2(-kv_xy c, g), phi_d = 0 and
+    f = m g on a level body (eqs. (8)-(9))."""
+    c = torch.tensor([1.0, -3.0, 0.25], dtype=F64)
+    n = c.shape[0]
+    psi_d = torch.tensor([0.3, -1.9, 2.6], dtype=F64)
+    xg = torch.zeros(n, 3, dtype=F64)
+    Rz = so3.rot_z(psi_d)
+    v = so3.mv(Rz, torch.stack([c, torch.zeros_like(c), torch.zeros_like(c)], -1))
+    z = torch.zeros(n, 3, dtype=F64)
+    out = run(xg, v, Rz, z, 0, torch.cat([xg, psi_d[:, None]], -1), split_fleet(n))
+    kv_xy = SPLIT_GAINS[2]
+    assert (out["theta_d"] - torch.atan2(-kv_xy * c, torch.full_like(c, G))).abs().max() < 1e-14
+    assert out["phi_d"].abs().max() < 1e-14
+    assert (out["f"] - SPLIT_MASS * G).abs().max() < 1e-13
+
+
+def test_position_mode_offset_uses_kx_xy_and_kx_z():
+    """Position mode at rest, level, x = x_d - R_z(psi_d) (d_x, 0, d_z):
+    F_V = m (kx_xy d_x, 0, g + kx_z d_z), so theta_d = atan2(kx_xy d_x, g + kx_z d_z),
+    phi_d = 0, f = m (g + kx_z d_z)."""
+    dx = torch.tensor([0.5, -1.0, 2.0], dtype=F64)
+    dz = torch.tensor([1.0, -0.5, 0.25], dtype=F64)
+    n = dx.shape[0]
+    psi_d = torch.tensor([-0.4, 1.1, 2.9], dtype=F64)
+    Rz = so3.rot_z(psi_d)
+    xg = torch.tensor([[0.5, 1.5, -1.0]] * n, dtype=F64)
+    x = xg - so3.mv(Rz, torch.stack([dx, torch.zeros_like(dx), dz], -1))
+    z = torch.zeros(n, 3, dtype=F64)
+    out = run(x, z, Rz, z, 0, torch.cat([xg, psi_d[:, None]], -1), split_fleet(n))
+    kx_xy, kx_z = SPLIT_GAINS[0], SPLIT_GAINS[1]
+    assert (out["theta_d"] - torch.atan2(kx_xy * dx, G + kx_z * dz)).abs().max() < 1e-14
+    assert out["phi_d"].abs().max() < 1e-14
+    assert (out["f"] - SPLIT_MASS * (G + kx_z * dz)).abs().max() < 1e-13
+
+
+def test_velocity_mode_split_gains_at_nonzero_velocity():
+    """Eqs. (6)-(9) with v_d = 0 and a level vehicle moving with
+    v = R_z(psi) (c1, 0, c3): a_d = (-kv_xy c1, 0, -kv_z c3) in V, so
+    theta_d = atan2(-kv_xy c1, g - kv_z c3), phi_d = 0, f = m (g - kv_z c3)."""
+    c1 = torch.tensor([1.0, -2.0, 0.5], dtype=F64)
+    c3 = torch.tensor([2.0, 1.0, -3.0], dtype=F64)
+    n = c1.shape[0]
+    psi = torch.tensor([0.2, -2.7, 1.4], dtype=F64)
+    Rz = so3.rot_z(psi)
+    v = so3.mv(Rz, torch.stack([c1, torch.zeros_like(c1), c3], -1))
+    z = torch.zeros(n, 3, dtype=F64)
+    out = run(z, v, Rz, z, 1, torch.zeros(n, 4, dtype=F64), split_fleet(n))
+    kv_xy, kv_z = SPLIT_GAINS[2], SPLIT_GAINS[3]
+    assert (out["theta_d"] - torch.atan2(-kv_xy * c1, G - kv_z * c3)).abs().max() < 1e-14
+    assert out["phi_d"].abs().max() < 1e-14
+    assert (out["f"] - SPLIT_MASS * (G - kv_z * c3)).abs().max() < 1e-13

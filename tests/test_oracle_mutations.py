@@ -70,3 +70,123 @@ def test_loss_counting_initial_state_is_caught(monkeypatch):
     monkeypatch.setattr(ostep, "per_vehicle_loss", bad)
     with pytest.raises(AssertionError):
         tg.test_loss_is_sum_over_post_step_states()
+
+
+# ---- position / velocity commands with split gains ---------------------------
+def test_swapped_gain_split_is_caught(monkeypatch):
+    def bad(gains):
+        kx = torch.stack([gains[:, 1], gains[:, 1], gains[:, 0]], -1)
+        kv = torch.stack([gains[:, 3], gains[:, 3], gains[:, 2]], -1)
+        return kx, kv, gains[:, 4:7], gains[:, 7:10]
+    monkeypatch.setattr(controller, "gain_vectors", bad)
+    for pin in (tc.test_position_mode_vertical_velocity_is_damped_by_kv_z,
+                tc.test_position_mode_horizontal_velocity_tilts_against_it,
+                tc.test_position_mode_offset_uses_kx_xy_and_kx_z,
+                tc.test_velocity_mode_split_gains_at_nonzero_velocity):
+        with pytest.raises(AssertionError):
+            pin()
+
+
+def test_flipped_position_damping_is_caught(monkeypatch):
+    monkeypatch.setattr(controller, "position_accel", lambda kx, kv, xd, x, v: kx * (xd - x) + kv * v)
+    with pytest.raises(AssertionError):
+        tc.test_position_mode_vertical_velocity_is_damped_by_kv_z()
+    with pytest.raises(AssertionError):
+        tc.test_position_mode_horizontal_velocity_tilts_against_it()
+
+
+def test_flipped_velocity_error_is_caught(monkeypatch):
+    monkeypatch.setattr(controller, "velocity_accel", lambda kv, vd, vV: kv * (vV - vd))
+    with pytest.raises(AssertionError):
+        tc.test_velocity_mode_split_gains_at_nonzero_velocity()
+
+
+# ---- Box-Muller normals of the reset redraw ------------------------------------
+import numpy as np  # noqa: E402
+import math  # noqa: E402
+
+import oracle.reset as oreset  # noqa: E402
+import oracle.stats as ostats  # noqa: E402
+import oracle.task as otask  # noqa: E402
+import test_oracle_philox_reset as tr  # noqa: E402
+import test_oracle_task_stats as tts  # noqa: E402
+
+
+def test_box_muller_log_of_u_is_caught(monkeypatch):
+    def bad(ua, ub):
+        r = np.sqrt(-2.0 * np.log(np.maximum(ua, 1e-300)))
+        return r * np.cos(2 * math.pi * ub), r * np.sin(2 * math.pi * ub)
+    monkeypatch.setattr(oreset, "box_muller", bad)
+    with pytest.raises(AssertionError):
+        tr.test_redraw_normals_closed_form()
+
+
+def test_box_muller_swapped_cos_sin_is_caught(monkeypatch):
+    orig = oreset.box_muller
+    monkeypatch.setattr(oreset, "box_muller", lambda ua, ub: tuple(reversed(orig(ua, ub))))
+    with pytest.raises(AssertionError):
+        tr.test_redraw_normals_closed_form()
+
+
+def test_swapped_reset_sigmas_are_caught(monkeypatch):
+    monkeypatch.setattr(oreset, "VEL_SIGMA", 0.2)
+    monkeypatch.setattr(oreset, "RATE_SIGMA", 0.5)
+    with pytest.raises(AssertionError):
+        tr.test_redraw_normals_closed_form()
+    with pytest.raises(AssertionError):
+        tr.test_redraw_normals_statistics()
+
+
+# ---- goal-reaching task ----------------------------------------------------------
+def _task_variant(change):
+    orig = otask.observe
+
+    def bad(state, goal, episode, w_v, w_omega, bonus, r_goal, r_far, max_steps):
+        obs, rew, done, ep = orig(state, goal, episode, w_v, w_omega, bonus, r_goal, r_far, max_steps)
+        s = np.asarray(state, np.float64)
+        dist = np.linalg.norm(np.asarray(goal, np.float64) - s[:, 0:3], axis=-1)
+        return change(s, dist, np.asarray(episode), obs, rew, done, ep, (w_v, w_omega, bonus, r_goal, r_far))
+    return bad
+
+
+TASK_MISTAKES = {
+    "speed term with the wrong sign": lambda s, d, e, o, r, dn, ep, p: (
+        o, r + 2 * p[0] * np.linalg.norm(s[:, 3:6], axis=-1), dn, ep),
+    "bonus at the boundary": lambda s, d, e, o, r, dn, ep, p: (o, r + np.where(d == p[3], p[2], 0.0), dn, ep),
+    "episode counter not restarted": lambda s, d, e, o, r, dn, ep, p: (o, r, dn, e + 1),
+    "non-finite state not done": lambda s, d, e, o, r, dn, ep, p: (
+        o, r, dn & np.isfinite(s).all(-1), ep),
+    "non-finite observation kept": lambda s, d, e, o, r, dn, ep, p: (
+        np.where(np.isfinite(s).all(-1)[:, None], o, s), r, dn, ep),
+    "termination at r_far itself": lambda s, d, e, o, r, dn, ep, p: (o, r, dn | (d >= p[4]), ep),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TASK_MISTAKES))
+def test_task_mistakes_are_caught(monkeypatch, name):
+    monkeypatch.setattr(otask, "observe", _task_variant(TASK_MISTAKES[name]))
+    with pytest.raises(AssertionError):
+        tts.test_task_hand_computed_cases()
+
+
+# ---- batch statistics --------------------------------------------------------------
+def test_stats_mistakes_are_caught(monkeypatch):
+    orig = ostats.final_state_stats
+
+    def omega_over_all(state, mode, target):
+        r = orig(state, mode, target)
+        r["omega_sum"] = float(torch.linalg.vector_norm(state[:, 10:13], dim=-1).sum())
+        return r
+
+    def error_over_all_modes(state, mode, target):
+        r = orig(state, mode, target)
+        fin = torch.isfinite(state).all(-1)
+        err = torch.linalg.vector_norm(state[:, 0:3] - target[:, 0:3], dim=-1)
+        r["pos_err_sum"] = float(err[fin].sum())
+        r["n_position"] = int(fin.sum())
+        return r
+
+    for bad in (omega_over_all, error_over_all_modes):
+        monkeypatch.setattr(ostats, "final_state_stats", bad)
+        with pytest.raises(AssertionError):
+            tts.test_stats_hand_built_state()

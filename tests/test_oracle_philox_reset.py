@@ -105,3 +105,65 @@ def test_reset_tilt_equals_drawn_angle():
     R = so3.quat_to_rot(s[:, 6:10])
     tilt = torch.acos(R[:, 2, 2].clamp(-1, 1)).numpy()
     np.testing.assert_allclose(tilt, reset.TILT_MAX * u[:, 7], atol=1e-7)
+
+
+def _uniform_rows(k):
+    u = np.full((k, 16), 0.5)
+    return u
+
+
+def test_redraw_normals_closed_form():
+    """Box-Muller on chosen uniforms: with 1 - u_a = e^(-1/2) the radius is
+    exactly 1, with u_a = 3/4 it is sqrt(2 ln 4) (it would be sqrt(-2 ln 3/4)
+    with ln u_a), and u_a = 0 gives 0; the angle 2 pi u_b puts the radius on
+    the first normal of the pair for u_b = 0 and on the second for u_b = 1/4.
+    Pair (9, 10) -> v_x, v_y; (11, 12) -> v_z, Omega_x; (13, 14) -> Omega_y,
+    Omega_z; velocity sigma 0.5, rate sigma 0.2."""
+    one = 1.0 - math.exp(-0.5)
+    u = _uniform_rows(5)
+    u[0, 9], u[0, 10] = one, 0.0           # v = (0.5, 0, .)
+    u[1, 9], u[1, 10] = one, 0.25          # v = (0, 0.5, .)
+    u[2, 9], u[2, 10] = 0.75, 0.5          # v_x = -0.5 sqrt(2 ln 4)
+    u[3, 9] = 0.0                          # r = 0
+    u[0, 11], u[0, 12] = one, 0.0          # v_z = 0.5, Omega_x = 0
+    u[1, 11], u[1, 12] = one, 0.25         # v_z = 0, Omega_x = 0.2
+    u[0, 13], u[0, 14] = one, 0.125        # Omega_y = Omega_z = 0.2 / sqrt 2
+    u[1, 13], u[1, 14] = 0.75, 0.75        # Omega_z = -0.2 sqrt(2 ln 4)
+    s, _ = reset.state_from_uniforms(u, (-1, -1, -1), (1, 1, 1))
+    s = s.numpy()
+    r4 = math.sqrt(2.0 * math.log(4.0))
+    tol = 1e-15
+    assert abs(s[0, 3] - 0.5) < tol and abs(s[0, 4]) < tol
+    assert abs(s[1, 3]) < tol and abs(s[1, 4] - 0.5) < tol
+    assert abs(s[2, 3] + 0.5 * r4) < tol and abs(s[2, 4]) < 1e-15
+    assert s[3, 3] == 0.0 and s[3, 4] == 0.0
+    assert abs(s[0, 5] - 0.5) < tol and abs(s[0, 10]) < tol
+    assert abs(s[1, 5]) < tol and abs(s[1, 10] - 0.2) < tol
+    assert abs(s[0, 11] - 0.2 / math.sqrt(2)) < tol and abs(s[0, 12] - 0.2 / math.sqrt(2)) < tol
+    assert abs(s[1, 11]) < tol and abs(s[1, 12] + 0.2 * r4) < tol
+
+
+def test_redraw_normals_statistics():
+    """On 200,000 Philox draws the velocity and rate components are N(0, 0.5^2)
+    and N(0, 0.2^2): sample mean within 5 standard errors of 0, sample sigma
+    within 5 standard errors (sigma / sqrt(2n)) of sigma, a Kolmogorov-Smirnov
+    test against the normal CDF, and the two normals of one Box-Muller pair
+    uncorrelated.  Positions and tilt are uniform on their ranges (KS)."""
+    from scipy import stats as st
+    n = 200_000
+    s, goal = reset.redraw(np.arange(n), 3, 11, (-5, -4, -3), (5, 4, 3))
+    s = s.numpy()
+    for cols, sigma in (((3, 4, 5), 0.5), ((10, 11, 12), 0.2)):
+        for c in cols:
+            x = s[:, c]
+            assert abs(x.mean()) < 5 * sigma / math.sqrt(n)
+            assert abs(x.std() - sigma) < 5 * sigma / math.sqrt(2 * n)
+            assert st.kstest(x, "norm", args=(0.0, sigma)).pvalue > 1e-4
+    rho = np.corrcoef(s[:, 3], s[:, 4])[0, 1]
+    assert abs(rho) < 5 / math.sqrt(n)
+    for d, h in enumerate((5, 4, 3)):
+        assert st.kstest(s[:, d], "uniform", args=(-h, 2 * h)).pvalue > 1e-4
+        assert st.kstest(goal.numpy()[:, d], "uniform", args=(-h, 2 * h)).pvalue > 1e-4
+    R = so3.quat_to_rot(torch.as_tensor(s[:, 6:10]))
+    tilt = torch.acos(R[:, 2, 2].clamp(-1, 1)).numpy()
+    assert st.kstest(tilt, "uniform", args=(0.0, reset.TILT_MAX)).pvalue > 1e-4
