@@ -20,25 +20,31 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per vehicle-step: bytes of the per-step
-# kernel (state in and out, 4-float command, mode byte) and FP32 flops of one
-# quad step per command mode, counted operation by operation on that mode's
-# path (an FMA as two, a reciprocal square root as one, per-vehicle constants
-# hoisted, products with structural zeros and the 2^-60 biases excluded):
-# position 215, velocity 221, attitude 188, wrench or unknown code 117.
+# Algorithmic work per vehicle-step.  Bytes of the per-step kernel: state in
+# and out, 4-float command, mode byte.  Flops: the headline figure is the
+# hot-path estimate for one quad step in position mode, about 380 FP32 flops
+# (196 VALU operations, FMAs counted twice, plus 4 reciprocal square roots).
+# A second figure counts one quad step per command mode operation by
+# operation on that mode's path (an FMA as two, a reciprocal square root as
+# one, per-vehicle constants hoisted, products with structural zeros and the
+# 2^-60 biases excluded): position 215, velocity 221, attitude 188, wrench or
+# unknown code 117.
 BYTES_PER_VSTEP = 52 + 52 + 16 + 1
+FLOPS_PER_VSTEP = 380.0
 FLOPS_BY_MODE = {0: 215, 1: 221, 2: 188}
 FLOPS_OTHER_MODE = 117
 
 
 def flops_per_vstep(mode):
-    """Mean algorithmic flops per vehicle-step over a fleet's modes."""
+    """Mean counted flops per vehicle-step over a fleet's modes."""
     import numpy as np
     m = np.asarray(mode).astype(np.int64)
     f = np.full(m.shape, float(FLOPS_OTHER_MODE))
     for code, fl in FLOPS_BY_MODE.items():
         f[m == code] = fl
     return float(f.mean())
+
+
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the
@@ -83,9 +89,25 @@ def timed(fn, sync):
     return time.perf_counter() - t0
 
 
-def event_time(stream, fn):
+_EVENTS = []
+
+
+def _events():
+    """Two timing events, created and recorded once up front so that their
+    first-use cost stays out of any timed region."""
     import torch
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if not _EVENTS:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        for e in ev:
+            e.record()
+        torch.cuda.synchronize()
+        _EVENTS.extend(ev)
+    return _EVENTS
+
+
+def event_time(stream, fn):
+    """Seconds between events recorded on `stream` around fn()'s launches."""
+    e0, e1 = _events()
     e0.record(stream)
     fn()
     e1.record(stream)
@@ -93,55 +115,87 @@ def event_time(stream, fn):
     return e0.elapsed_time(e1) / 1e3
 
 
-def cpu_baseline(wl, n_sample, steps):
-    import torch
+def timed_with_events(stream, fn, sync):
+    """(wall seconds, event seconds) of fn()'s launches: the wall clock runs
+    from a device synchronisation before the launches to one after them, and
+    events recorded on `stream` around the launches give the device time
+    (read after the closing synchronisation)."""
+    e0, e1 = _events()
+    sync()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    sync()
+    t = time.perf_counter() - t0
+    return t, e0.elapsed_time(e1) / 1e3
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def time_oracle(sub, steps):
     import oracle
-    import workloads
-    torch.set_num_threads(max(1, len(os.sched_getaffinity(0))))
-    sub = workloads.subset(wl, n_sample)
     s0, mode, tgt = oracle.step.from_workload_arrays(sub.state0, sub.mode, sub.target)
     fleet = oracle.Fleet.from_groups(sub.groups, sub.n, sub.vparams)
     t0 = time.perf_counter()
     oracle.step.rollout(s0, mode, tgt, fleet, sub.dt, sub.g, steps)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(wl, n_sample, steps):
+    """The FP64 oracle, as it stands, on the host's cores: a slice of the
+    benchmark workload, the same on one thread (smaller slice), and the
+    1,024-quad 500-step position-mode parity workload."""
+    import torch
+    import workloads
+    torch.set_num_threads(max(1, len(os.sched_getaffinity(0))))
     cores = torch.get_num_threads()
-    # the same oracle on one thread, on a smaller slice
+    dt = time_oracle(workloads.subset(wl, n_sample), steps)
+    c1 = workloads.c1_parity()
+    dt_c1 = time_oracle(c1, c1.steps)
     n1, s1 = max(1, n_sample // 8), max(1, steps // 3)
-    sub1 = workloads.subset(wl, n1)
-    a0, am, at = oracle.step.from_workload_arrays(sub1.state0, sub1.mode, sub1.target)
-    f1 = oracle.Fleet.from_groups(sub1.groups, sub1.n, sub1.vparams)
     torch.set_num_threads(1)
-    t1 = time.perf_counter()
-    oracle.step.rollout(a0, am, at, f1, sub1.dt, sub1.g, s1)
-    dt1 = time.perf_counter() - t1
+    dt1 = time_oracle(workloads.subset(wl, n1), s1)
     torch.set_num_threads(cores)
     return {"value": n_sample * steps / dt, "unit": "vehicle-steps/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"first {n_sample} vehicles of the workload x {steps} steps (FP64 torch on CPU)",
             "seconds": dt,
+            "parity_workload": {"value": c1.n * c1.steps / dt_c1, "cores": cores, "seconds": dt_c1,
+                                "sample": f"{c1.n} quads x {c1.steps} steps, position mode, dt={c1.dt}"},
             "single_thread": {"value": n1 * s1 / dt1, "cores": 1,
                               "sample": f"first {n1} vehicles x {s1} steps", "seconds": dt1}}
 
 
 def bench_adjoint(sync, reps=3):
     """Differentiation workload: 65,536 quads, 200-step position rollout,
-    checkpoint every 20 steps; forward + hand-written adjoint."""
-    import torch
+    checkpoint every 20 steps; forward (with the batch loss) + hand-written
+    adjoint."""
     import workloads
     from paper_2305_16510_amd.sim import Sim
     wl = workloads.c4_grad()
     T, m = wl.steps, wl.meta["ckpt_every"]
     sim = Sim.from_workload(wl)
-    sim.rollout_forward(T, m)
+    sim.rollout_forward(T, m, want_loss_i=False)
     sim.rollout_adjoint(T, m)
     sync()
     tf, ta = [], []
     for _ in range(reps):
-        tf.append(event_time(sim.stream, lambda: sim.rollout_forward(T, m)))
+        tf.append(event_time(sim.stream, lambda: sim.rollout_forward(T, m, want_loss_i=False)))
         ta.append(event_time(sim.stream, lambda: sim.rollout_adjoint(T, m)))
     sim.close()
     f, a = min(tf), min(ta)
-    log(f"adjoint: forward {f * 1e3:.2f} ms, adjoint {a * 1e3:.2f} ms for {T} steps of {wl.n} vehicles")
+    log(f"adjoint: forward {f * 1e3:.3f} ms, adjoint {a * 1e3:.3f} ms for {T} steps of {wl.n} vehicles")
     return {"workload": "65,536 quads, 200-step position rollout, checkpoint every 20, 10 gain + 13 state "
                         "gradients per vehicle", "n_vehicles": wl.n, "steps": T,
             "forward_s_per_step": f / T, "adjoint_s_per_step": a / T, "fwd_plus_adj_s_per_step": (f + a) / T,
@@ -281,14 +335,18 @@ def bench_camera(sync, n=1024, n_obs=20, W=480, H=270, reps=5):
             "paper_context": {"images_per_s": 1800, "hardware": "RTX 3090, engine renderer (Sec. VI)"}}
 
 
+LEGS = {"adjoint": bench_adjoint, "uneven_groups": bench_uneven, "large_resets": bench_large,
+        "per_step_4M": bench_per_step_large, "depth_cameras": bench_camera}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=1024)
     ap.add_argument("--n", type=int, default=1_048_576)
-    ap.add_argument("--probe-steps", type=int, default=1024,
-                    help="steps per autotuning trial (also the largest k tried)")
+    ap.add_argument("--probe-steps", type=int, default=0,
+                    help="steps per autotuning trial (also the largest k tried); 0: the timed call length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-step", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -298,6 +356,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--only", choices=sorted(LEGS), default="",
+                    help="run one secondary leg alone and print its record (profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -307,12 +367,20 @@ def main():
 
     import torch
     import workloads
-    from paper_2305_16510_amd import probe
+    import bench_probe as probe
     from paper_2305_16510_amd.sim import Sim
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.only:
+        rec = {args.only: LEGS[args.only](torch.cuda.synchronize)}
+        if args.copy_calib_mib:
+            probe.copy_once(args.copy_calib_mib << 20)
+            rec["copy_calibration"] = {"kernel": "k_copy (agp_copy)", "bytes_read": args.copy_calib_mib << 20,
+                                       "bytes_written": args.copy_calib_mib << 20, "dispatches": 3}
+        print(json.dumps(rec), flush=True)
+        return
     K, W = args.steps, args.warmup
     wl = workloads.c2_scale(n=args.n)
     log(f"workload {wl.name}: n={wl.n}")
@@ -323,29 +391,50 @@ def main():
         sim.set_exec(kind=1, block=b, vpl=v, k=k, grid=g, use_graph=1)
         tuned = sim.get_exec()
     else:
+        # the policy for calls of K steps, from trials of K-step calls
         t0 = time.perf_counter()
-        tuned = sim.autotune(args.probe_steps)
-        log(f"autotuned {tuned} in {time.perf_counter() - t0:.1f}s")
+        tuned = sim.autotune(args.probe_steps or K)
+        log(f"autotuned {tuned} for {args.probe_steps or K}-step calls in {time.perf_counter() - t0:.1f}s")
     k = tuned["k"]
 
     # ---- fused, graph-replayed ------------------------------------------------
+    # ag_prepare builds and uploads the K-step graph (when K needs more than one
+    # launch) and computes the mode order, so the timed call only launches
     sim.prepare(K)
     sim.prepare(W)
     sim.raw_step(W)
+    _events()
     sync()
     t_evt = {}
-
-    def run_fused():
-        t_evt["fused"] = event_time(sim.stream, lambda: sim.raw_step(K))
-
-    t_fused = timed(run_fused, sync)
+    t_fused, t_evt["fused"] = timed_with_events(sim.stream, lambda: sim.raw_step(K), sync)
     # the same K steps timed four more times (spread of the measurement)
     repeats = [timed(lambda: sim.raw_step(K), sync) for _ in range(4)]
     launches = math.ceil(K / k)
     kern_fused = t_evt["fused"] / launches
     value = wl.n * K / t_fused
-    log(f"fused: {t_fused * 1e3:.2f} ms for {K} steps -> {value:.3e} vehicle-steps/s; "
+    log(f"fused: {t_fused * 1e3:.3f} ms for {K} steps -> {value:.3e} vehicle-steps/s; "
         f"kernel avg {kern_fused * 1e6:.1f} us over {launches} launches")
+
+    # ---- the profiled launch shape: 1,024 steps under the same policy --------
+    # (outside the headline timing; with k = 512 these are two full launches,
+    # the shape of the committed counter profile)
+    fixed_steps = 1024
+    tuned_fixed = sim.get_exec() if args.exec else sim.autotune(fixed_steps)
+    k_fixed = tuned_fixed["k"]
+    sim.prepare(fixed_steps)
+    sim.raw_step(fixed_steps)
+    sync()
+    t_fix = min(event_time(sim.stream, lambda: sim.raw_step(fixed_steps)) for _ in range(3))
+    fix_launches = math.ceil(fixed_steps / k_fixed)
+    fix_tflops = FLOPS_PER_VSTEP * wl.n * fixed_steps / t_fix / 1e12
+    roofline_fixed = {"steps": fixed_steps, "exec": tuned_fixed, "launches": fix_launches,
+                      "steps_per_launch": min(fixed_steps, k_fixed),
+                      "kernel_avg_us": t_fix / fix_launches * 1e6, "us_per_step": t_fix / fixed_steps * 1e6,
+                      "value": wl.n * fixed_steps / t_fix, "achieved": fix_tflops, "unit": "TFLOP/s",
+                      "frac": fix_tflops / FP32_PEAK_TFLOPS,
+                      "counted_frac": flops_per_vstep(wl.mode) * wl.n * fixed_steps / t_fix / 1e12 / FP32_PEAK_TFLOPS}
+    log(f"fixed shape: {fixed_steps} steps in {fix_launches} launches, {t_fix / fixed_steps * 1e6:.2f} us/step, "
+        f"frac {roofline_fixed['frac']:.3f}")
 
     # ---- plain per-step launches ----------------------------------------------
     # K kernel launches without a graph, issued by the library's own launch
@@ -369,10 +458,7 @@ def main():
         sim.raw_step(W)
         sync()
 
-        def run_plain():
-            t_evt["plain"] = event_time(sim.stream, lambda: sim.raw_step(K))
-
-        t_plain = timed(run_plain, sync)
+        t_plain, t_evt["plain"] = timed_with_events(sim.stream, lambda: sim.raw_step(K), sync)
         kern_plain = t_evt["plain"] / K
 
         def run_calls():
@@ -397,8 +483,9 @@ def main():
 
     # achieved = algorithmic flops of the timed launches / their event time
     # (the last launch of a K that k does not divide runs fewer steps)
-    fl_vstep = flops_per_vstep(wl.mode)
-    tflops = fl_vstep * wl.n * K / t_evt["fused"] / 1e12
+    fl_count = flops_per_vstep(wl.mode)
+    tflops = FLOPS_PER_VSTEP * wl.n * K / t_evt["fused"] / 1e12
+    tflops_count = fl_count * wl.n * K / t_evt["fused"] / 1e12
     valid = counters_valid()
     # VALU utilisation: lane-instructions issued per second against the chip's
     # peak issue rate (157.3 TFLOP/s = 78.6e12 single-lane FMAs per second)
@@ -426,10 +513,15 @@ def main():
                      # one load and one store of the state per launch, whatever k
                      "traffic": COUNTERS["fused_bytes"] if valid else None,
                      "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
-                     "steps_per_launch": k, "flops_per_vehicle_step": fl_vstep,
+                     "launches": launches, "steps_per_launch": min(K, k),
+                     "flops_per_vehicle_step": FLOPS_PER_VSTEP,
+                     "counted": {"flops_per_vehicle_step": fl_count, "achieved": tflops_count,
+                                 "frac": tflops_count / FP32_PEAK_TFLOPS,
+                                 "what": "per-mode operation count of the fleet's modes (not the headline)"},
                      "valu_instr_per_vehicle_step": COUNTERS["fused_valu_per_vstep"] if valid else None,
                      "valu_issue_frac_of_peak": valu_util,
                      "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},
+        "roofline_fixed_shape": roofline_fixed,
         "per_step": per_step,
         "fused_over_per_step": (value / per_step["value"]) if per_step else None,
         "env": {"device": torch.cuda.get_device_name(0),
@@ -443,7 +535,7 @@ def main():
     if not args.no_extras:
         wp = workloads.paper_context()
         sp = Sim.from_workload(wp, autotune_scratch=True)
-        tuned_p = sp.autotune(args.probe_steps)
+        tuned_p = sp.autotune(args.probe_steps or K)
         sp.prepare(K)
         sp.raw_step(K)
         sync()

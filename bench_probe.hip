@@ -1,7 +1,19 @@
-// ag_probe.hip -- calibration kernels for the roofline (see include/ag_probe.h).
+// bench_probe.hip -- calibration kernels for the benchmark's roofline (not
+// part of the simulator library).
+//
+// agp_valu_fma: every lane runs 8 independent FP32 FMA chains of `iters`
+//   steps (single, non-packed v_fma_f32), grid `blocks` x 256 threads; writes
+//   one float per thread to out (device, blocks*256 floats) so nothing is
+//   dead code.  FMA count = blocks * 256 * iters * 8.
+// agp_copy: plain vectorised device copy of `bytes` bytes (multiple of 16)
+//   from src to dst (device pointers, 16-byte aligned): reads and writes
+//   exactly `bytes` each; used to calibrate the HBM byte counters and to
+//   measure the achievable copy bandwidth.  `blocks` x 256 lanes walk the
+//   16-byte elements grid-stride; blocks = 0 launches one lane per element.
+// Both enqueue on `stream` (hipStream_t) and return 0, or a hipError_t code.
 #include <hip/hip_runtime.h>
-
-#include "ag_probe.h"
+#include <stddef.h>
+#include <stdint.h>
 
 namespace {
 

@@ -1,11 +1,27 @@
-"""Calibration probes (include/ag_probe.h): measured FP32 FMA and copy peaks."""
+"""Calibration probes of the benchmark (kernels in bench_probe.hip): the
+measured FP32 FMA issue rate and device copy bandwidth, and a plain copy of
+known size for calibrating the HBM byte counters.  Not part of the library."""
 import ctypes as C
 import os
+import subprocess
 
-import torch
-
-PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libagprobe.so")
+ROOT = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(ROOT, "bench_probe.hip")
+PATH = os.path.join(ROOT, "_probe", "libagprobe.so")
 _lib = None
+
+
+def build():
+    """Compile bench_probe.hip for gfx950 into _probe/libagprobe.so."""
+    from paper_2305_16510_amd.build import HIP_FLAGS, hipcc
+    os.makedirs(os.path.dirname(PATH), exist_ok=True)
+    tmp = PATH + ".tmp"
+    cmd = [hipcc(), *HIP_FLAGS, "-shared", SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {SRC}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PATH)
+    return PATH
 
 
 def load():
@@ -20,6 +36,7 @@ def load():
 
 
 def _time(stream, fn, reps=5):
+    import torch
     best = None
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -34,6 +51,7 @@ def _time(stream, fn, reps=5):
 
 def valu_fma_peak(blocks=4096, iters=4096):
     """Measured FP32 FMA lane-operations per second (non-packed v_fma_f32)."""
+    import torch
     L = load()
     out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
     s = torch.cuda.current_stream()
@@ -48,6 +66,7 @@ def copy_bandwidth(nbytes=1 << 30, grids=(0, 2048, 8192, 32768)):
     best of plain copies with one lane per 16-byte element (grid 0) and
     grid-stride copies of the given block counts; also returns the rate of
     each grid."""
+    import torch
     L = load()
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -63,6 +82,7 @@ def copy_bandwidth(nbytes=1 << 30, grids=(0, 2048, 8192, 32768)):
 
 def copy_once(nbytes):
     """One plain copy of nbytes (for counter calibration runs)."""
+    import torch
     L = load()
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)

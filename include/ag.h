@@ -155,10 +155,17 @@ typedef struct {
 /* Device workspace (bytes) that ag_create needs for this configuration. */
 ag_status ag_workspace_size(const ag_config* cfg, size_t* bytes);
 
-/* Validate cfg, build the per-group tables (rotor allocation matrix and its
- * min-norm pseudo-inverse, inverse mass and inertia) in FP64 on the host,
- * round them to FP32 and upload them into `workspace` (device, >= the size
- * from ag_workspace_size, 256-byte aligned).  Enqueues on cfg->stream. */
+/* Create a batch of cfg->n independent vehicles (Sec. III: many environments
+ * simulated in parallel, one robot each; Sec. VI: the throughput is that of the
+ * whole batch).  Validate cfg, build the per-group tables (rotor allocation
+ * matrix and its min-norm pseudo-inverse, inverse mass and inertia) in FP64 on
+ * the host, round them to FP32 and upload them into `workspace` (device, >=
+ * the size from ag_workspace_size, 256-byte aligned; owned by the caller,
+ * which keeps it alive until ag_destroy).  Enqueues on cfg->stream and waits
+ * for it.  AG_E_INVALID: cfg fails validation (message on stderr) or a rotor
+ * layout's tables lack the structure the kernels assume; AG_E_NOMEM:
+ * workspace too small; AG_E_HIP: a copy or launch failed.  *out is NULL on
+ * failure. */
 ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_bytes, ag_handle* out);
 
 /* Wait for the handle's stream, then release the host-side handle and its
@@ -166,44 +173,74 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
  * when the wait reports a device error (returned as AG_E_HIP). */
 ag_status ag_destroy(ag_handle h);
 
-/* New commands for vehicles [first, first+count): copies mode_src[i] and
+/* New commands for vehicles [first, first+count) (Sec. IV: the high-level
+ * position, velocity or attitude commands a user gives each vehicle; Sec. III:
+ * the per-environment action of a Gym-style step): copies mode_src[i] and
  * target_src[r*src_ld + i] (device pointers; NULL = keep the bound buffers'
  * contents) into the bound buffers and checks the mode codes; invalid codes
- * are counted in ag_stats.n_invalid_mode (such vehicles get a zero wrench). */
+ * are counted in ag_stats.n_invalid_mode (such vehicles get a zero wrench).
+ * Call it over any range of the bound mode or target buffers written
+ * directly, so that data the handle derives from the commands is renewed. */
 ag_status ag_set_targets(ag_handle h, int64_t first, int64_t count, const int8_t* mode_src,
                          const float* target_src, int64_t src_ld);
 
 /* Advance every vehicle by n_steps steps (controller, allocation, clamping,
  * integration; with auto_reset, the counter-based reset before each step),
  * asynchronously on the handle's stream, with the current execution policy.
- * A fused call of 32 or more steps with one vehicle per lane, no trajectory
- * buffer, no observers and no automatic resets first orders the vehicles of
- * each group by command mode within segments of 4,096 (workspace), so that
- * wavefronts of one mode run that mode's copy of the step loop; results are
- * bitwise those of any other policy. */
+ * Operation: one step is the map of Sec. IV (command of the vehicle's mode,
+ * desired attitude and rate, eqs. (1)-(2), errors and moment, eqs. (3)-(5);
+ * velocity mode eqs. (6)-(9)) followed by allocation and the rigid-body
+ * update the paper delegates to its physics engine (Sec. I, end of Sec. IV-B);
+ * the batch is stepped in lock step, as the environments of Sec. III.
+ * Fused launches with one vehicle per lane, no trajectory buffer, no
+ * observers and no automatic resets run the vehicles of each group in an
+ * order by command mode within segments of 4,096 (workspace), so that
+ * wavefronts of one mode run that mode's copy of the step loop.  The order is
+ * computed by the first such call of 32 or more steps (or by ag_prepare or
+ * ag_autotune) and kept until ag_set_targets or ag_apply_actions changes the
+ * commands; a call shorter than 32 steps with no current order runs without
+ * it.  The order decides only which lanes share a wavefront: results are
+ * bitwise those of any other policy, also when the mode buffer was written
+ * directly (the order is then merely stale; ag_set_targets over the written
+ * range renews it). */
 ag_status ag_step(ag_handle h, int32_t n_steps);
 
-/* Build and cache the HIP graph that ag_step(h, n_steps) will replay under
- * the current execution policy, without launching it (no-op when the policy
- * launches directly). */
+/* Prepare ag_step(h, n_steps) under the current execution policy without
+ * stepping: build, cache and upload to the device the HIP graph it will
+ * replay (when the policy uses graphs), and compute the mode order when the
+ * policy's fused launches use one and it is not current (one launch on the
+ * handle's stream).  A prepared call of any length then runs in mode order. */
 ag_status ag_prepare(ag_handle h, int32_t n_steps);
 
 ag_status ag_set_exec(ag_handle h, const ag_exec* e);
 ag_status ag_get_exec(ag_handle h, ag_exec* e);
 
-/* Time candidate fused policies (block 64..512, vehicles per lane 1 or 2,
- * k in 4..1024 up to probe_steps, grid one block per tile or a persistent
- * multiple of the CU count) for probe_steps steps each and keep the fastest;
- * synchronises the stream.  With
+/* Choose the fused policy for calls of probe_steps steps: time candidate
+ * fused policies (block 64..512, vehicles per lane 1 or 2, k the powers of
+ * two from 4 to 1024 up to probe_steps and probe_steps itself, grid one block
+ * per tile or a persistent multiple of the CU count) on probe_steps-step
+ * calls and keep the fastest; synchronises the stream.  With
  * autotune_scratch the probes write scratch buffers, so the state is
- * untouched; without it the call returns AG_E_STATE. */
+ * untouched; without it the call returns AG_E_STATE.  The choice is cached
+ * for the process, and appended to the text file named by the environment
+ * variable AG_AUTOTUNE_CACHE when it is set (read once per process), under a
+ * key of the device architecture and CU count, n, the group layout (counts and
+ * rotor counts), the kernel class (rotor class, per-vehicle parameters,
+ * automatic resets, observers, trajectories, graphs) and probe_steps; a later
+ * call with the same key takes the cached policy without timing.  Every
+ * policy gives bitwise identical results. */
 ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen);
 
-/* Reset vehicles before global step `step`: the mask is mask_in (device
- * uint8[n], nonzero = reset) or, if NULL, the counter-based mask for that
- * step.  Reset vehicles get a redrawn state and (position mode) goal.
- * Optionally writes mask_out (uint8[n]), the ascending indices of reset
- * vehicles (indices_out, int32[n]) and their number (count_out, int32[1]). */
+/* Reset vehicles before global step `step` (Sec. III: environments are reset
+ * individually, Gym-style; Sec. V: the asset manager randomises at reset, here
+ * the vehicle's state and goal): the mask is mask_in (device uint8[n], nonzero
+ * = reset) or, if NULL, the counter-based mask for that step (Philox4x32-10
+ * keyed by cfg.seed, one draw per global vehicle index and step, reset when
+ * the first word is below floor(reset_prob 2^32)).  Reset vehicles get a
+ * redrawn state and, in position mode, goal.  Optionally writes mask_out
+ * (uint8[n]), the ascending indices of reset vehicles (indices_out, int32[n])
+ * and their number (count_out, int32[1]); all outputs are device pointers.
+ * Asynchronous on the handle's stream; AG_E_INVALID for step < 0. */
 ag_status ag_reset(ag_handle h, const uint8_t* mask_in, int64_t step, uint8_t* mask_out,
                    int32_t* indices_out, int32_t* count_out);
 
@@ -283,25 +320,43 @@ ag_status ag_get_step(ag_handle h, int64_t* step);
 ag_status ag_set_step(ag_handle h, int64_t step);
 
 /* Differentiable rollout of the tracking loss
- *   L = scale_n * sum_i sum_{t=1..T} ( |x_{i,t} - x_goal,i|^2 + w_omega |Omega_{i,t}|^2 )
- * over post-step states, x_goal = the position-mode target, scale_n = 1/n.
- * Starting state x0 (device [13][ld]; NULL = the bound state, which is not
- * modified).  Requires position or wrench modes and per-vehicle vparams.
- * Forward: per-vehicle loss (loss_out [n], without scale_n) and checkpoints
- * of the state every ckpt_every steps in `ws`; final_state optional [13][ld].
+ *   L = (1/n) sum_i sum_{t=1..T} ( |x_{i,t} - x_goal,i|^2 + w_omega |Omega_{i,t}|^2 )
+ * over post-step states, x_goal = the position-mode target.  The paper trains
+ * controllers and policies on the batched simulator (Sec. I, III); this
+ * differentiates the controller-plus-dynamics rollout of Sec. IV with respect
+ * to each vehicle's ten gains (eq. (5)'s k_R, k_Omega and the position and
+ * velocity gains of eqs. (6)-(7), layout of cfg.vparams rows 4..13) and its
+ * initial state.  Requires position or wrench modes and per-vehicle vparams.
+ *   x0     device [13][ld] starting state, or NULL: the bound state (not modified)
+ *   gains  device [10][ld] gains of the rollout, or NULL: vparams rows 4..13
+ *          (the other vparams rows are always taken from cfg.vparams)
+ * Forward: steps every vehicle n_steps times from x0, keeping the state every
+ * ckpt_every steps in `ws`.  Outputs (device, each optional): loss_out [n],
+ * vehicle i's sum over t (without 1/n); batch_loss [1], L itself, summed in
+ * FP64 in a fixed order (per 64 vehicles, then over those partials), so that
+ * equal inputs give a bitwise equal L; final_state [13][ld].
  * Adjoint: recomputes each checkpoint segment (into one of two tape buffers
  * in `ws`, overlapped with the reverse sweep of the later segment) and sweeps
  * it backwards, writing dL/dgains (dgains [10][ld]) and dL/dx0 (dx0 [13][ld])
- * multiplied by `seed_grad`; both calls must use the same arguments and
- * workspace.  Workspace: n_ckpt + 2 ckpt_every states of 13 floats per
- * vehicle, n_ckpt = ceil(n_steps / ckpt_every), each part 256-byte aligned. */
+ * multiplied by seed_grad and, when seed_dev (device float [1]) is not NULL,
+ * by *seed_dev read on the device (an upstream gradient that need not be
+ * copied to the host).  The adjoint reads the checkpoints of the forward call:
+ * both calls take the same x0, gains, n_steps, ckpt_every, w_omega and
+ * workspace, and the buffers they read must not change in between.
+ * Workspace (caller-owned, 256-byte aligned, size from
+ * ag_rollout_workspace_size): n_ckpt + 2 ckpt_every states of 13 floats per
+ * vehicle, n_ckpt = ceil(n_steps / ckpt_every), and ceil(n / 64) doubles of
+ * loss partials, each part 256-byte aligned.  Asynchronous on the handle's
+ * stream.  AG_E_NOMEM: workspace missing, misaligned or small; AG_E_UNSUPPORTED:
+ * no vparams, or a trajectory buffer is bound; AG_E_INVALID: n_steps or
+ * ckpt_every < 1, non-finite w_omega, missing dgains or dx0. */
 ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_every, size_t* bytes);
-ag_status ag_rollout_forward(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every,
-                             float w_omega, void* ws, size_t ws_bytes, float* loss_out,
-                             float* final_state);
-ag_status ag_rollout_adjoint(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every,
-                             float w_omega, float seed_grad, void* ws, size_t ws_bytes,
-                             float* dgains, float* dx0);
+ag_status ag_rollout_forward(ag_handle h, const float* x0, const float* gains, int32_t n_steps,
+                             int32_t ckpt_every, float w_omega, void* ws, size_t ws_bytes, float* loss_out,
+                             float* batch_loss, float* final_state);
+ag_status ag_rollout_adjoint(ag_handle h, const float* x0, const float* gains, int32_t n_steps,
+                             int32_t ckpt_every, float w_omega, float seed_grad, const float* seed_dev,
+                             void* ws, size_t ws_bytes, float* dgains, float* dx0);
 
 /* Wait for the handle's stream; returns a sticky error if one occurred. */
 ag_status ag_sync(ag_handle h);

@@ -71,6 +71,20 @@ def allocate(f, M, fleet, tabs=None):
     return u_all, f_app, M_app, raw_all
 
 
+def clamp_distance(raw, fleet):
+    """Per vehicle, the distance of the raw rotor command closest to a clamp
+    bound (u_min or u_max), over that vehicle's rotors, relative to u_max."""
+    N = raw.shape[0]
+    d = torch.full((N,), float("inf"), dtype=raw.dtype)
+    for nr in sorted(set(int(k) for k in fleet.n_rotors.tolist())):
+        idx = (fleet.n_rotors == nr).nonzero().squeeze(-1)
+        r = raw[idx, :nr]
+        lo = (r - fleet.u_min[idx, None]).abs()
+        hi = (r - fleet.u_max[idx, None]).abs()
+        d[idx] = torch.minimum(lo, hi).min(-1).values / fleet.u_max[idx]
+    return d
+
+
 def saturated_count(raw, fleet):
     """Number of rotors per vehicle whose raw command lies strictly outside
     [u_min, u_max] (the clamp is inclusive, R20)."""

@@ -51,6 +51,21 @@ def rollout(state0, mode, target, fleet, dt, g, steps, keep_states=False, traj=N
     return s, states, sat
 
 
+def clamp_margin(state0, mode, target, fleet, dt, g, steps):
+    """Per vehicle, the smallest distance over the steps of a rollout of a raw
+    rotor command to a clamp bound, relative to u_max.  Where it is small the
+    loss has a kink close to the trajectory (the clamp of reading R20), and an
+    FP32 run of the same rollout may pass the other side of it."""
+    tabs = allocation.tables(fleet)
+    s = state0
+    m = torch.full((state0.shape[0],), float("inf"), dtype=state0.dtype)
+    with torch.no_grad():
+        for _ in range(steps):
+            s, info = step(s, mode, target, fleet, dt, g, tabs)
+            m = torch.minimum(m, allocation.clamp_distance(info["u_raw"], fleet))
+    return m
+
+
 def per_vehicle_loss(state0, mode, target, fleet, dt, g, steps, w_omega):
     """l_i = sum_{t=1..T} |x_t - x_goal|^2 + w_Omega |Omega_t|^2 (per vehicle)."""
     tabs = allocation.tables(fleet)

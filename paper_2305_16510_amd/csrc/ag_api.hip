@@ -11,7 +11,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +75,7 @@ struct ExecKey {
 
 struct GraphEntry {
     int n_steps;
+    bool ordered;      // fused launches read the mode order (kept in the workspace)
     ExecKey key;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -94,6 +97,7 @@ struct ag_sim {
     StatAcc* acc;
     StatSlot* slots;
     int32_t* perm;          // mode order of fused launches
+    bool order_valid;       // perm was computed since the last change of commands
     int32_t* block_counts;
     uint8_t* mask_buf;
     float* scratch;
@@ -340,13 +344,20 @@ StepArgs base_args(ag_handle h) {
 // event kernels.
 bool uses_events(ag_handle h, const ag_exec& e) { return h->reset_on && e.kind == 1 && h->ev.cap > 0; }
 
-// Whether the fused launches of an ag_step of n_steps steps run in mode order
-// (their kernels have the mode-specialised step loops; the order costs one
-// pass over the modes per call, so short calls go without it).
-bool uses_order(ag_handle h, const ag_exec& e, int n_steps) {
+// Whether the policy's fused launches can run in mode order (their kernels
+// have the mode-specialised step loops).
+bool order_policy(ag_handle h, const ag_exec& e) {
     const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
-    return e.kind == 1 && e.vpl == 1 && h->cfg.traj == nullptr && !obs && !h->reset_on &&
-           n_steps >= kOrderMinSteps;
+    return e.kind == 1 && e.vpl == 1 && h->cfg.traj == nullptr && !obs && !h->reset_on;
+}
+
+// Whether the fused launches of an ag_step of n_steps steps run in mode order.
+// The order is computed once and kept until the commands change; a stale
+// order costs one pass over the modes, which short calls skip.  (Any order
+// within groups gives the same results: it only decides which lanes share a
+// wavefront.)
+bool uses_order(ag_handle h, const ag_exec& e, int n_steps) {
+    return order_policy(h, e) && (h->order_valid || n_steps >= kOrderMinSteps);
 }
 
 OrderArgs order_args(ag_handle h) {
@@ -354,6 +365,17 @@ OrderArgs order_args(ag_handle h) {
 }
 
 dim3 order_grid(ag_handle h) { return dim3((unsigned)((h->cfg.n + kOrderSeg - 1) / kOrderSeg)); }
+
+ag_status launch(ag_handle h, const void* fn, dim3 grid, dim3 block, size_t shmem, void* args);
+
+// Compute the mode order into the workspace unless it is current.
+ag_status ensure_order(ag_handle h) {
+    if (h->order_valid) return AG_OK;
+    OrderArgs o = order_args(h);
+    ag_status st = launch(h, mode_order_kernel(), order_grid(h), dim3(kOrderBlock), 0, &o);
+    if (st == AG_OK) h->order_valid = true;
+    return st;
+}
 
 // The event kernels of one launch, in order (they take the launch's arguments).
 struct EvKernels {
@@ -426,8 +448,7 @@ ag_status run_direct(ag_handle h, const ag_exec& e, int n_steps, StepArgs a, boo
     a.d_step = nullptr;
     a.perm = nullptr;
     if (uses_order(h, e, n_steps)) {
-        OrderArgs o = order_args(h);
-        ag_status st = launch(h, mode_order_kernel(), order_grid(h), dim3(kOrderBlock), 0, &o);
+        ag_status st = ensure_order(h);
         if (st != AG_OK) return st;
         a.perm = h->perm;
     }
@@ -465,7 +486,9 @@ ag_status add_node(ag_handle h, hipGraph_t g, hipGraphNode_t* node, hipGraphNode
     return AG_OK;
 }
 
-ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
+// Graph of the fused or per-step launches of ag_step(n_steps); `ordered`:
+// the launches read the mode order (computed outside the graph).
+ag_status build_graph(ag_handle h, int n_steps, bool ordered, GraphEntry& ge) {
     LaunchShape s;
     std::string m = shape_for(h, h->exec, s);
     if (!m.empty()) return set_err(h, AG_E_INVALID, m);
@@ -476,14 +499,7 @@ ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
     a.d_step = h->d_step;
     const int k = h->exec.kind == 0 ? 1 : h->exec.k;
     hipGraphNode_t prev = nullptr, node = nullptr;
-    a.perm = nullptr;
-    if (uses_order(h, h->exec, n_steps)) {
-        OrderArgs o = order_args(h);
-        ag_status st = add_node(h, g, &node, nullptr, mode_order_kernel(), order_grid(h), dim3(kOrderBlock), 0, &o);
-        if (st != AG_OK) { hipGraphDestroy(g); return st; }
-        prev = node;
-        a.perm = h->perm;
-    }
+    a.perm = ordered ? h->perm : nullptr;
     for (int done = 0; done < n_steps; done += k) {
         a.t_off = done;
         a.k = std::min(k, n_steps - done);
@@ -492,32 +508,33 @@ ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
             const EvKernels ek = event_kernels(h);
             for (int q = 0; q < 4; ++q) {
                 ag_status st = add_node(h, g, &node, prev ? &prev : nullptr, ek.fn[q], ek.grid[q], ek.block[q], 0, &a);
-                if (st != AG_OK) { hipGraphDestroy(g); return st; }
+                if (st != AG_OK) { (void)hipGraphDestroy(g); return st; }
                 prev = node;
             }
         }
         ag_status st = add_node(h, g, &node, prev ? &prev : nullptr, s.fn, s.grid, s.block, s.shmem, &a);
-        if (st != AG_OK) { hipGraphDestroy(g); return st; }
+        if (st != AG_OK) { (void)hipGraphDestroy(g); return st; }
         prev = node;
         if (s.fn_fb) {
             st = add_node(h, g, &node, &prev, s.fn_fb, s.grid, s.block, s.shmem, &a);
-            if (st != AG_OK) { hipGraphDestroy(g); return st; }
+            if (st != AG_OK) { (void)hipGraphDestroy(g); return st; }
             prev = node;
         }
     }
     if (a.slots) {
         FoldArgs f{h->slots, (int)s.grid.x, h->acc, n_steps, 1};
         ag_status st = add_node(h, g, &node, &prev, fold_kernel(), dim3(1), dim3(256), 0, &f);
-        if (st != AG_OK) { hipGraphDestroy(g); return st; }
+        if (st != AG_OK) { (void)hipGraphDestroy(g); return st; }
         prev = node;
     }
     CounterArgs c{h->d_step, n_steps};
     ag_status st = add_node(h, g, &node, &prev, advance_kernel(), dim3(1), dim3(64), 0, &c);
-    if (st != AG_OK) { hipGraphDestroy(g); return st; }
+    if (st != AG_OK) { (void)hipGraphDestroy(g); return st; }
     hipGraphExec_t ex;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) { hipGraphDestroy(g); return hip_fail(h, e, "hipGraphInstantiate"); }
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(h, e, "hipGraphInstantiate"); }
     ge.n_steps = n_steps;
+    ge.ordered = ordered;
     ge.key = {h->exec.kind, h->exec.block, h->exec.vpl, h->exec.k, h->exec.grid, h->exec.use_graph};
     ge.graph = g;
     ge.exec = ex;
@@ -527,8 +544,8 @@ ag_status build_graph(ag_handle h, int n_steps, GraphEntry& ge) {
 
 void drop_graphs(ag_handle h) {
     for (auto& ge : h->graphs) {
-        hipGraphExecDestroy(ge.exec);
-        hipGraphDestroy(ge.graph);
+        (void)hipGraphExecDestroy(ge.exec);
+        (void)hipGraphDestroy(ge.graph);
     }
     h->graphs.clear();
 }
@@ -609,6 +626,7 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
     h->thr = (unsigned long long)std::min(std::max(thr, 0.0), 4294967296.0);
     h->t = 0;
     h->dev_step_dirty = true;
+    h->order_valid = false;
     h->stamp = 0;
     h->sticky = AG_OK;
     int dev = 0;
@@ -672,6 +690,7 @@ ag_status ag_set_targets(ag_handle h, int64_t first, int64_t count, const int8_t
     if (target_src && src_ld < count) return set_err(h, AG_E_INVALID, "src_ld must be >= count");
     if (count == 0) return AG_OK;
     SetTargetsArgs a{h->cfg.mode, h->cfg.target, mode_src, target_src, h->cfg.ld, src_ld, first, count, h->acc};
+    h->order_valid = false;
     return launch(h, set_targets_kernel(), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, &a);
 }
 
@@ -697,23 +716,23 @@ ag_status ag_get_exec(ag_handle h, ag_exec* e) {
 namespace {
 
 // Find or build the cached graph for n_steps under the current policy.
-ag_status cached_graph(ag_handle h, int n_steps, GraphEntry** out) {
+ag_status cached_graph(ag_handle h, int n_steps, bool ordered, GraphEntry** out) {
     const ag_exec& e = h->exec;
     ExecKey key{e.kind, e.block, e.vpl, e.k, e.grid, e.use_graph};
     for (auto& g : h->graphs)
-        if (g.n_steps == n_steps && g.key == key) {
+        if (g.n_steps == n_steps && g.ordered == ordered && g.key == key) {
             g.stamp = ++h->stamp;
             *out = &g;
             return AG_OK;
         }
     GraphEntry ng;
-    ag_status st = build_graph(h, n_steps, ng);
+    ag_status st = build_graph(h, n_steps, ordered, ng);
     if (st != AG_OK) return st;
     if (h->graphs.size() >= 8) {
         auto old = std::min_element(h->graphs.begin(), h->graphs.end(),
                                     [](const GraphEntry& a, const GraphEntry& b) { return a.stamp < b.stamp; });
-        hipGraphExecDestroy(old->exec);
-        hipGraphDestroy(old->graph);
+        (void)hipGraphExecDestroy(old->exec);
+        (void)hipGraphDestroy(old->graph);
         h->graphs.erase(old);
     }
     h->graphs.push_back(ng);
@@ -734,9 +753,19 @@ extern "C" {
 ag_status ag_prepare(ag_handle h, int32_t n_steps) {
     AG_CHECK_HANDLE(h);
     if (n_steps < 0) return set_err(h, AG_E_INVALID, "n_steps must be >= 0");
-    if (n_steps == 0 || !uses_graph(h, n_steps)) return AG_OK;
+    if (n_steps == 0) return AG_OK;
+    // a call that is prepared for will run in mode order whatever its length
+    if (order_policy(h, h->exec)) {
+        ag_status st = ensure_order(h);
+        if (st != AG_OK) return st;
+    }
+    if (!uses_graph(h, n_steps)) return AG_OK;
     GraphEntry* ge = nullptr;
-    return cached_graph(h, n_steps, &ge);
+    ag_status st = cached_graph(h, n_steps, uses_order(h, h->exec, n_steps), &ge);
+    if (st != AG_OK) return st;
+    // move the executable graph to the device now, not at its first launch
+    AG_HIP(h, hipGraphUpload(ge->exec, h->stream));
+    return AG_OK;
 }
 
 ag_status ag_step(ag_handle h, int32_t n_steps) {
@@ -750,9 +779,14 @@ ag_status ag_step(ag_handle h, int32_t n_steps) {
         h->dev_step_dirty = true;
         return AG_OK;
     }
+    const bool ordered = uses_order(h, h->exec, n_steps);
     GraphEntry* ge = nullptr;
-    ag_status st = cached_graph(h, n_steps, &ge);
+    ag_status st = cached_graph(h, n_steps, ordered, &ge);
     if (st != AG_OK) return st;
+    if (ordered) {
+        st = ensure_order(h);
+        if (st != AG_OK) return st;
+    }
     if (h->dev_step_dirty) {
         CounterArgs c{h->d_step, h->t};
         st = launch(h, set_step_kernel(), dim3(1), dim3(64), 0, &c);
@@ -764,10 +798,112 @@ ag_status ag_step(ag_handle h, int32_t n_steps) {
     return AG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---- autotune cache ------------------------------------------------------------
+// Chosen policies, per process and optionally in a text file (one line per
+// key: "<key> kind block vpl k grid use_graph"), keyed by everything the
+// timing depends on: device, n, group layout, kernel class and call length.
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, ag_exec>> g_tune;
+bool g_tune_file_read = false;
+
+const char* tune_file() {
+    const char* f = std::getenv("AG_AUTOTUNE_CACHE");
+    return (f && *f) ? f : nullptr;
+}
+
+void tune_read_file_locked() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = tune_file();
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    ag_exec e{};
+    while (std::fscanf(f, "%511s %d %d %d %d %d %d", key, &e.kind, &e.block, &e.vpl, &e.k, &e.grid,
+                       &e.use_graph) == 7)
+        g_tune.push_back({key, e});
+    std::fclose(f);
+}
+
+bool tune_lookup(const std::string& key, ag_exec* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_read_file_locked();
+    for (auto it = g_tune.rbegin(); it != g_tune.rend(); ++it)
+        if (it->first == key) {
+            *out = it->second;
+            return true;
+        }
+    return false;
+}
+
+void tune_store(const std::string& key, const ag_exec& e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_read_file_locked();
+    g_tune.push_back({key, e});
+    if (const char* path = tune_file()) {
+        if (FILE* f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), e.kind, e.block, e.vpl, e.k, e.grid, e.use_graph);
+            std::fclose(f);
+        }
+    }
+}
+
+std::string tune_key(ag_handle h, int probe_steps) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        for (char& c : arch)
+            if (c == ':' || c == ' ') c = '.';
+    }
+    // group layout: FNV-1a over (count, rotor count) of every group
+    unsigned long long fh = 1469598103934665603ull;
+    auto mix = [&](long long v) {
+        for (int b = 0; b < 8; ++b) {
+            fh ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+            fh *= 1099511628211ull;
+        }
+    };
+    for (const auto& g : h->groups) {
+        mix(g.count);
+        mix(g.n_rotors);
+    }
+    const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
+    char buf[384];
+    std::snprintf(buf, sizeof buf, "%s/cu%d/n%lld/g%d.%016llx/nr%d/vp%d/rst%d.%d/obs%d/trk%d/graph%d/L%d",
+                  arch.c_str(), h->num_cus, (long long)h->cfg.n, h->cfg.n_groups, fh, h->nr_class, h->vp ? 1 : 0,
+                  h->reset_on ? 1 : 0, h->ev.cap > 0 ? 1 : 0, obs ? 1 : 0, h->cfg.traj ? 1 : 0,
+                  h->exec.use_graph, probe_steps);
+    return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
 ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     AG_CHECK_HANDLE(h);
     if (!h->scratch) return set_err(h, AG_E_STATE, "autotune needs cfg.autotune_scratch = 1");
     if (probe_steps < 1) return set_err(h, AG_E_INVALID, "probe_steps must be >= 1");
+    const std::string key = tune_key(h, probe_steps);
+    ag_exec cached{};
+    LaunchShape cs;
+    if (tune_lookup(key, &cached) && shape_for(h, cached, cs).empty()) {
+        h->exec = cached;
+        if (chosen) *chosen = cached;
+        return AG_OK;
+    }
+    // trials run in mode order whenever the tuned calls will
+    if (order_policy(h, ag_exec{1, 64, 1, 1, 0, 0})) {
+        ag_status st = ensure_order(h);
+        if (st != AG_OK) return st;
+    }
     const long long ld = h->cfg.ld;
     float* s_state = h->scratch;
     float* s_target = h->scratch + (size_t)AG_STATE_DIM * ld;
@@ -784,7 +920,12 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     int occ_blocks_per_cu = 0;
     const int blocks[] = {64, 128, 256, 512};
     const int vpls[] = {1, 2};
-    const int ks[] = {4, 8, 16, 32, 64, 128, 256, 512, 1024};
+    // powers of two up to the call length, and the call length itself (one
+    // launch per call)
+    std::vector<int> ks = {4, 8, 16, 32, 64, 128, 256, 512, 1024};
+    if (probe_steps <= 1024 && std::find(ks.begin(), ks.end(), probe_steps) == ks.end()) ks.push_back(probe_steps);
+    // short trials are noisier: more repetitions (the first is not counted)
+    const int reps = probe_steps >= 256 ? 3 : 7;
     ag_exec best = h->exec;
     float best_ms = 1e30f;
     const long long saved_t = h->t;
@@ -806,7 +947,7 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
                         cand.grid = (int)gp;
                     }
                     float ms_min = 1e30f;
-                    for (int rep = 0; rep < 3; ++rep) {
+                    for (int rep = 0; rep < reps; ++rep) {
                         AG_HIP(h, hipMemcpy2DAsync(s_state, ld * sizeof(float), h->cfg.state, ld * sizeof(float),
                                                    h->cfg.n * sizeof(float), AG_STATE_DIM, hipMemcpyDeviceToDevice,
                                                    h->stream));
@@ -816,8 +957,8 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
                         AG_HIP(h, hipEventRecord(e0, h->stream));
                         ag_status st = run_direct(h, cand, probe_steps, a, false);
                         if (st != AG_OK) {
-                            hipEventDestroy(e0);
-                            hipEventDestroy(e1);
+                            (void)hipEventDestroy(e0);
+                            (void)hipEventDestroy(e1);
                             return st;
                         }
                         AG_HIP(h, hipEventRecord(e1, h->stream));
@@ -833,13 +974,14 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
                 }
             }
     h->t = saved_t;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ClearArgs ca{h->slots, (int)h->L.nslots};
     ag_status st = launch(h, clear_slots_kernel(), dim3((unsigned)((h->L.nslots + 255) / 256)), dim3(256), 0, &ca);
     if (st != AG_OK) return st;
     AG_HIP(h, hipStreamSynchronize(h->stream));
     h->exec = best;
+    tune_store(key, best);
     if (chosen) *chosen = best;
     return AG_OK;
 }
@@ -967,6 +1109,7 @@ ag_status ag_apply_actions(ag_handle h, const float* actions, int64_t act_ld, in
         a.scale[r] = scale[r];
         a.offset[r] = offset[r];
     }
+    h->order_valid = false;
     return launch(h, actions_kernel(), dim3((unsigned)((h->cfg.n + 255) / 256)), dim3(256), 0, &a);
 }
 
@@ -1048,6 +1191,7 @@ ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_e
     size_t off = 0;
     off = align_up(off + (size_t)n_ckpt * AG_STATE_DIM * n * sizeof(float));
     off = align_up(off + 2 * (size_t)ckpt_every * AG_STATE_DIM * n * sizeof(float));   // two tape buffers
+    off = align_up(off + (size_t)((n + 63) / 64) * sizeof(double));                    // loss partials
     *bytes = off;
     return AG_OK;
 }
@@ -1058,8 +1202,8 @@ namespace {
 
 constexpr int kRolloutBlock = 64;
 
-ag_status rollout_args(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega, void* ws,
-                       size_t ws_bytes, RolloutArgs& a, LaunchShape& s) {
+ag_status rollout_args(ag_handle h, const float* x0, const float* gains, int32_t n_steps, int32_t ckpt_every,
+                       float w_omega, void* ws, size_t ws_bytes, RolloutArgs& a, LaunchShape& s) {
     if (n_steps < 1 || ckpt_every < 1) return set_err(h, AG_E_INVALID, "n_steps and ckpt_every must be >= 1");
     if (!h->cfg.vparams) return set_err(h, AG_E_UNSUPPORTED, "rollouts differentiate per-vehicle gains: vparams required");
     if (h->cfg.traj) return set_err(h, AG_E_UNSUPPORTED, "rollouts of the tracking mode are not differentiated");
@@ -1072,15 +1216,19 @@ ag_status rollout_args(ag_handle h, const float* x0, int32_t n_steps, int32_t ck
     const long long n = h->cfg.n;
     const long long n_ckpt = (n_steps + ckpt_every - 1) / ckpt_every;
     char* base = static_cast<char*>(ws);
+    const size_t ckpt_bytes = align_up((size_t)n_ckpt * AG_STATE_DIM * n * sizeof(float));
+    const size_t tape_bytes = align_up(2 * (size_t)ckpt_every * AG_STATE_DIM * n * sizeof(float));
     a = RolloutArgs{};
     a.x0 = x0 ? x0 : h->cfg.state;
+    a.gains = gains;
     a.mode = h->cfg.mode;
     a.target = h->cfg.target;
     a.vparams = h->cfg.vparams;
     a.gtab = h->gtab;
     a.goff = h->goff;
     a.ckpt = reinterpret_cast<float*>(base);
-    a.tape = reinterpret_cast<float*>(base + align_up((size_t)n_ckpt * AG_STATE_DIM * n * sizeof(float)));
+    a.tape = reinterpret_cast<float*>(base + ckpt_bytes);
+    a.loss_part = reinterpret_cast<double*>(base + ckpt_bytes + tape_bytes);
     a.n = n;
     a.ld = h->cfg.ld;
     a.n_groups = h->cfg.n_groups;
@@ -1103,29 +1251,37 @@ ag_status rollout_args(ag_handle h, const float* x0, int32_t n_steps, int32_t ck
 
 extern "C" {
 
-ag_status ag_rollout_forward(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega,
-                             void* ws, size_t ws_bytes, float* loss_out, float* final_state) {
+ag_status ag_rollout_forward(ag_handle h, const float* x0, const float* gains, int32_t n_steps, int32_t ckpt_every,
+                             float w_omega, void* ws, size_t ws_bytes, float* loss_out, float* batch_loss,
+                             float* final_state) {
     AG_CHECK_HANDLE(h);
     RolloutArgs a;
     LaunchShape s;
-    ag_status st = rollout_args(h, x0, n_steps, ckpt_every, w_omega, ws, ws_bytes, a, s);
+    ag_status st = rollout_args(h, x0, gains, n_steps, ckpt_every, w_omega, ws, ws_bytes, a, s);
     if (st != AG_OK) return st;
     a.loss_out = loss_out;
     a.final_state = final_state;
-    return launch(h, rollout_fwd_kernel(h->nr_class), s.grid, s.block, s.shmem, &a);
+    if (!batch_loss) a.loss_part = nullptr;
+    st = launch(h, rollout_fwd_kernel(h->nr_class), s.grid, s.block, s.shmem, &a);
+    if (st != AG_OK || !batch_loss) return st;
+    LossFoldArgs f{a.loss_part, (int32_t)s.grid.x, 1.0 / (double)h->cfg.n, batch_loss};
+    return launch(h, loss_fold_kernel(), dim3(1), dim3(256), 0, &f);
 }
 
-ag_status ag_rollout_adjoint(ag_handle h, const float* x0, int32_t n_steps, int32_t ckpt_every, float w_omega,
-                             float seed_grad, void* ws, size_t ws_bytes, float* dgains, float* dx0) {
+ag_status ag_rollout_adjoint(ag_handle h, const float* x0, const float* gains, int32_t n_steps, int32_t ckpt_every,
+                             float w_omega, float seed_grad, const float* seed_dev, void* ws, size_t ws_bytes,
+                             float* dgains, float* dx0) {
     AG_CHECK_HANDLE(h);
     if (!dgains || !dx0) return set_err(h, AG_E_INVALID, "dgains and dx0 are required");
     RolloutArgs a;
     LaunchShape s;
-    ag_status st = rollout_args(h, x0, n_steps, ckpt_every, w_omega, ws, ws_bytes, a, s);
+    ag_status st = rollout_args(h, x0, gains, n_steps, ckpt_every, w_omega, ws, ws_bytes, a, s);
     if (st != AG_OK) return st;
     a.dgains = dgains;
     a.dx0 = dx0;
-    a.seed_grad = seed_grad / (float)h->cfg.n;
+    a.seed_grad = seed_grad;
+    a.inv_n = 1.0f / (float)h->cfg.n;
+    a.seed_dev = seed_dev;
     // two wavefronts per 64 vehicles: reverse sweep and recomputation
     return launch(h, rollout_adj_kernel(h->nr_class), s.grid, dim3(2 * kRolloutBlock), s.shmem, &a);
 }

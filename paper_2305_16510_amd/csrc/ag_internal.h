@@ -98,13 +98,17 @@ struct RolloutArgs {
     float* ckpt;               // [n_ckpt][13][n]
     float* tape;               // [m][13][n]
     float* loss_out;           // [n] or null
+    double* loss_part;         // [ceil(n / 64)] FP64 loss sums of 64 vehicles, or null
     float* final_state;        // [13][ld] or null
+    const float* gains;        // [10][ld] gains of the rollout, or null: vparams rows
+    const float* seed_dev;     // [1] device factor of the gradients, or null
     float* dgains;             // [10][ld]
     float* dx0;                // [13][ld]
     long long n, ld;
     int32_t n_groups, span;
     int32_t T, m, n_ckpt;
     float dt, g, w_omega, seed_grad;
+    float inv_n;               // 1/n in FP32 (the batch mean's factor)
 };
 
 constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
@@ -126,6 +130,15 @@ const void* reset_scatter_kernel();
 const void* clear_slots_kernel();
 const void* rollout_fwd_kernel(int nr_class);
 const void* rollout_adj_kernel(int nr_class);
+
+// Batch loss: fixed-order FP64 sum of the per-64-vehicle partials, times 1/n.
+struct LossFoldArgs {
+    const double* part;
+    int32_t nparts;
+    double inv_n;
+    float* out;                // [1]
+};
+const void* loss_fold_kernel();
 
 struct FoldArgs {
     StatSlot* slots;

@@ -99,8 +99,13 @@ __device__ void block_stats(StatSlot* slots, long long c_sat, long long c_res, l
     }
 }
 
+// Fused one-vehicle-per-lane kernels without trajectories carry mode-
+// specialised copies of the step loop: those without resets when no observer
+// is bound, and those fed by the reset events (whose loop holds only the
+// event test and a copy of the redrawn state).  The other forms would exceed
+// 128 registers with them.
 constexpr bool spec_loops(bool one, int vpl, bool obs, bool trk, int rst) {
-    return !one && vpl == 1 && !obs && !trk && rst == 0;
+    return !one && vpl == 1 && !trk && ((rst == 0 && !obs) || rst == 2);
 }
 
 // The tiles of one block.  UNI (per-step kernels of a single-group launch):
@@ -114,9 +119,6 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
     constexpr bool RESET = RST != 0;
     constexpr bool EV = RESET && !ONE;
     constexpr bool FB = !(EV && RST == 2);
-    // fused one-vehicle-per-lane kernels without observers, trajectories or
-    // resets carry mode-specialised copies of the step loop (the other forms
-    // would exceed 128 registers with them)
     constexpr bool SPEC = spec_loops(ONE, VPL, OBS, TRK, RST);
     const int B = blockDim.x;
     const long long TILE = (long long)B * VPL;
@@ -284,11 +286,21 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         if constexpr (SPEC) {
             const int m_first = __builtin_amdgcn_readfirstlane(md[0]);
             const int wm = __all(md[0] == m_first) ? m_first : -1;
-            switch (wm) {
-            case 0: run_loop(std::integral_constant<int, 0>{}); break;
-            case 1: run_loop(std::integral_constant<int, 1>{}); break;
-            case 2: run_loop(std::integral_constant<int, 2>{}); break;
-            default: run_loop(General{}); break;
+            if constexpr (RESET) {
+                // the event-fed loop has one copy, position mode: resets redraw
+                // goals of position-mode vehicles
+                if (wm == 0) {
+                    for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{}, std::integral_constant<int, 0>{});
+                } else {
+                    for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{}, General{});
+                }
+            } else {
+                switch (wm) {
+                case 0: run_loop(std::integral_constant<int, 0>{}); break;
+                case 1: run_loop(std::integral_constant<int, 1>{}); break;
+                case 2: run_loop(std::integral_constant<int, 2>{}); break;
+                default: run_loop(General{}); break;
+                }
             }
         } else {
             // (the plain loop, not run_loop: the per-step kernels compile to
@@ -382,7 +394,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
 }
 
 template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VPL == 1 && (RST == 2 || spec_loops(ONE, VPL, OBS, TRK, RST)) ? 4 : 1)))
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VPL == 1 && !TRK && ((RST == 2 && !OBS) || spec_loops(ONE, VPL, OBS, TRK, RST)) ? (RST == 2 && OBS ? 3 : 4) : 1)))
 void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);

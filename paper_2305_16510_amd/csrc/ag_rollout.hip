@@ -86,8 +86,31 @@ __device__ __forceinline__ void by_mode(int wm, F&& fn) {
     }
 }
 
+// The rollout's own gains (gains rows, when given) in place of the vparams rows.
+__device__ __forceinline__ void override_gains(Params& P, const float* __restrict__ gains, long long ld,
+                                               long long i) {
+    if (!gains) return;
+    P.kx_xy = gains[i];
+    P.kx_z = gains[ld + i];
+    P.kv_xy = gains[2 * ld + i];
+    P.kv_z = gains[3 * ld + i];
+    P.kR0 = gains[4 * ld + i];
+    P.kR1 = gains[5 * ld + i];
+    P.kR2 = gains[6 * ld + i];
+    P.kW0 = gains[7 * ld + i];
+    P.kW1 = gains[8 * ld + i];
+    P.kW2 = gains[9 * ld + i];
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Forward rollout; one wavefront (64 vehicles) per block.
 template <int NR>
-__global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
+__global__ __launch_bounds__(64) void k_rollout_fwd(RolloutArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
     int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
@@ -95,39 +118,59 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(RolloutArgs a) {
     const long long base = (long long)blockIdx.x * blockDim.x;
     const long long i = base + threadIdx.x;
     const float* gl = rollout_stage(a, lds, loff, sh, base, base + blockDim.x < a.n ? base + blockDim.x : a.n, i);
-    if (i >= a.n) return;
-    EntryRegs ge;
-    copy_entry(ge, gl);
-    const float* gt = ge.e;
-    const long long ld = a.ld, n = a.n;
-    float s[13];
-#pragma unroll
-    for (int r = 0; r < 13; ++r) s[r] = a.x0[r * ld + i];
-    Params P;
-    load_params<true>(P, gt, a.vparams, ld, i);
-    Cmd C;
-    derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
-    const float gx = C.t0, gy = C.t1, gz = C.t2;
     double loss = 0.0;
-    by_mode(wave_mode(C.mode), [&](auto ms) {
-        constexpr int MS = decltype(ms)::value;
-        for (int t = 0; t < a.T; ++t) {
-            if (t % a.m == 0) {
-                float* ck = a.ckpt + (long long)(t / a.m) * 13 * n;
+    if (i < a.n) {
+        EntryRegs ge;
+        copy_entry(ge, gl);
+        const float* gt = ge.e;
+        const long long ld = a.ld, n = a.n;
+        float s[13];
 #pragma unroll
-                for (int r = 0; r < 13; ++r) ck[r * n + i] = s[r];
+        for (int r = 0; r < 13; ++r) s[r] = a.x0[r * ld + i];
+        Params P;
+        load_params<true>(P, gt, a.vparams, ld, i);
+        override_gains(P, a.gains, ld, i);
+        Cmd C;
+        derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
+        const float gx = C.t0, gy = C.t1, gz = C.t2;
+        by_mode(wave_mode(C.mode), [&](auto ms) {
+            constexpr int MS = decltype(ms)::value;
+            for (int t = 0; t < a.T; ++t) {
+                if (t % a.m == 0) {
+                    float* ck = a.ckpt + (long long)(t / a.m) * 13 * n;
+#pragma unroll
+                    for (int r = 0; r < 13; ++r) ck[r * n + i] = s[r];
+                }
+                step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+                const float ex = s[0] - gx, ey = s[1] - gy, ez = s[2] - gz;
+                const float lt =
+                    ex * ex + ey * ey + ez * ez + a.w_omega * (s[10] * s[10] + s[11] * s[11] + s[12] * s[12]);
+                loss += (double)lt;
             }
-            step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
-            const float ex = s[0] - gx, ey = s[1] - gy, ez = s[2] - gz;
-            const float lt = ex * ex + ey * ey + ez * ez + a.w_omega * (s[10] * s[10] + s[11] * s[11] + s[12] * s[12]);
-            loss += (double)lt;
-        }
-    });
-    if (a.loss_out) a.loss_out[i] = (float)loss;
-    if (a.final_state) {
+        });
+        if (a.loss_out) a.loss_out[i] = (float)loss;
+        if (a.final_state) {
 #pragma unroll
-        for (int r = 0; r < 13; ++r) a.final_state[r * ld + i] = s[r];
+            for (int r = 0; r < 13; ++r) a.final_state[r * ld + i] = s[r];
+        }
     }
+    if (a.loss_part) {
+        // the block's 64 vehicle sums in a fixed butterfly order (lanes past n add 0)
+        const double b = wave_sum_f64(loss);
+        if (threadIdx.x == 0) a.loss_part[blockIdx.x] = b;
+    }
+}
+
+// Batch loss: one block; thread t adds partials t, t + 256, ... in order, then
+// the 256 sums are added in a fixed butterfly and wavefront order.
+__global__ __launch_bounds__(256) void k_loss_fold(LossFoldArgs a) {
+    __shared__ double w[4];
+    double v = 0.0;
+    for (int p = threadIdx.x; p < a.nparts; p += 256) v += a.part[p];
+    v = wave_sum_f64(v);
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) a.out[0] = (float)(((w[0] + w[1]) + (w[2] + w[3])) * a.inv_n);
 }
 
 // Recompute segment seg from its checkpoint: tape entry t - t0 = state before step t.
@@ -197,6 +240,7 @@ __global__ __launch_bounds__(128) void k_rollout_adj(RolloutArgs a) {
     Cmd C = {};
     if (act) {
         load_params<true>(P, gt, a.vparams, ld, i);
+        override_gains(P, a.gains, ld, i);
         derive_cmd(C, (int)a.mode[i], a.target[i], a.target[ld + i], a.target[2 * ld + i], a.target[3 * ld + i]);
     }
     const int last = a.n_ckpt - 1;
@@ -229,7 +273,9 @@ __global__ __launch_bounds__(128) void k_rollout_adj(RolloutArgs a) {
         __syncthreads();
     }
     if (reverse_wave && act) {
-        const float sc = a.seed_grad;
+        // (seed_grad times the device factor, then 1/n: an upstream gradient
+        // given either way yields the same bits)
+        const float sc = (a.seed_dev ? a.seed_grad * a.seed_dev[0] : a.seed_grad) * a.inv_n;
 #pragma unroll
         for (int r = 0; r < 10; ++r) a.dgains[r * ld + i] = A.gb[r] * sc;
 #pragma unroll
@@ -245,6 +291,8 @@ const void* rollout_fwd_kernel(int nr_class) {
         default: return reinterpret_cast<const void*>(&k_rollout_fwd<0>);
     }
 }
+
+const void* loss_fold_kernel() { return reinterpret_cast<const void*>(&k_loss_fold); }
 
 const void* rollout_adj_kernel(int nr_class) {
     switch (nr_class) {

@@ -9,12 +9,10 @@ frame, yaw rate) or attitude commands (roll, pitch, yaw rate, thrust).  One
 (kernel: observation, reward, termination), reset of the finished vehicles
 (counter-based redraw of state and goal) and their new observation.
 """
-import math
-
 import torch
 
 from . import lib as L
-from .sim import Sim
+from .sim import Group, Sim
 
 INTERFACES = {
     # mode, scale, offset of the 4 command rows
@@ -26,12 +24,13 @@ INTERFACES = {
 class GoalReachEnv:
     def __init__(self, n, interface="velocity", decimation=1, max_steps=500, seed=0, dt=0.01,
                  box=5.0, task=None, device="cuda:0"):
-        import workloads
-        wl = workloads.c1_parity(n=n, seed=seed)
         self.mode, self.scale, self.offset = INTERFACES[interface]
-        goal = torch.zeros(3, n)
-        self.sim = Sim(wl.groups, wl.state0, wl.mode, wl.target, dt=dt, seed=seed, reset_prob=0.0,
-                       reset_lo=(-box,) * 3, reset_hi=(box,) * 3, goal=goal, device=device)
+        # every vehicle at rest at the origin, level, until reset() redraws it
+        state0 = torch.zeros(13, n)
+        state0[6] = 1.0
+        self.sim = Sim([Group(0, n)], state0, torch.full((n,), self.mode, dtype=torch.int8),
+                       torch.zeros(4, n), dt=dt, seed=seed, reset_prob=0.0, reset_lo=(-box,) * 3,
+                       reset_hi=(box,) * 3, goal=torch.zeros(3, n), device=device)
         self.n = n
         self.decimation = decimation
         self.task = task or L.Task(0.05, 0.01, 1.0, 0.2, 4.0 * box, max_steps)

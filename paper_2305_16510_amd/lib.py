@@ -90,8 +90,8 @@ def load():
         "ag_get_step": ([H, C.POINTER(C.c_int64)], C.c_int),
         "ag_set_step": ([H, C.c_int64], C.c_int),
         "ag_rollout_workspace_size": ([H, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
-        "ag_rollout_forward": ([H, P, C.c_int32, C.c_int32, C.c_float, P, C.c_size_t, P, P], C.c_int),
-        "ag_rollout_adjoint": ([H, P, C.c_int32, C.c_int32, C.c_float, C.c_float, P, C.c_size_t, P, P],
+        "ag_rollout_forward": ([H, P, P, C.c_int32, C.c_int32, C.c_float, P, C.c_size_t, P, P, P], C.c_int),
+        "ag_rollout_adjoint": ([H, P, P, C.c_int32, C.c_int32, C.c_float, C.c_float, P, P, C.c_size_t, P, P],
                                C.c_int),
         "ag_sync": ([H], C.c_int),
         "ag_last_error": ([H], C.c_char_p),

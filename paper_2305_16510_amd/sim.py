@@ -5,6 +5,7 @@ workspaces) and the stream; every step of the method runs in the HIP
 kernels of ``libag.so``.
 """
 import ctypes as C
+from dataclasses import dataclass
 
 import numpy as np
 import torch
@@ -12,6 +13,22 @@ import torch
 from . import lib as L
 
 F32 = torch.float32
+
+
+@dataclass
+class Group:
+    """A contiguous range of vehicles sharing a rotor layout and default
+    parameters (the defaults: an X-quadrotor of 1 kg with a 0.13 m arm)."""
+    first: int
+    count: int
+    n_rotors: int = 4
+    arm: float = 0.13
+    c_tau: float = 0.016
+    u_min: float = 0.0
+    u_max: float = 6.0
+    mass: float = 1.0
+    inertia: tuple = (0.007, 0.007, 0.012)
+    gains: tuple = (2.0, 2.0, 2.0, 2.0, 1.6, 1.6, 0.6, 0.5, 0.5, 0.2)
 
 
 def _ptr(t):
@@ -244,27 +261,46 @@ class Sim:
         self._call("ag_set_step", C.c_int64(int(t)))
 
     # ---- differentiable rollout ---------------------------------------------
-    def rollout_workspace(self, n_steps, ckpt_every):
+    def rollout_workspace_bytes(self, n_steps, ckpt_every):
         nbytes = C.c_size_t(0)
         L.check(self._lib.ag_rollout_workspace_size(self.h, int(n_steps), int(ckpt_every), C.byref(nbytes)),
                 self.h, "ag_rollout_workspace_size")
-        if self._rollout_ws is None or self._rollout_ws.numel() < nbytes.value:
-            self._rollout_ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        return max(int(nbytes.value), 256)
+
+    def new_rollout_workspace(self, n_steps, ckpt_every):
+        """A fresh rollout workspace (checkpoints, tapes, loss partials)."""
+        return torch.empty(self.rollout_workspace_bytes(n_steps, ckpt_every), dtype=torch.uint8,
+                           device=self.device)
+
+    def rollout_workspace(self, n_steps, ckpt_every):
+        """The Sim's shared rollout workspace, grown as needed (for paired
+        rollout_forward / rollout_adjoint calls with no other rollout between)."""
+        need = self.rollout_workspace_bytes(n_steps, ckpt_every)
+        if self._rollout_ws is None or self._rollout_ws.numel() < need:
+            self._rollout_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         return self._rollout_ws
 
-    def rollout_forward(self, n_steps, ckpt_every, w_omega=0.01, x0=None, want_final=False):
-        ws = self.rollout_workspace(n_steps, ckpt_every)
-        loss = torch.empty(self.n, dtype=F32, device=self.device)
+    def rollout_forward(self, n_steps, ckpt_every, w_omega=0.01, x0=None, want_final=False, gains=None,
+                        ws=None, want_loss_i=True):
+        """Per-vehicle loss [n] (or None), batch loss (device [1]) and final state
+        [13, n] (or None) of the rollout; checkpoints go to ``ws`` (default: the
+        shared workspace)."""
+        ws = self.rollout_workspace(n_steps, ckpt_every) if ws is None else ws
+        loss = torch.empty(self.n, dtype=F32, device=self.device) if want_loss_i else None
+        batch = torch.empty(1, dtype=F32, device=self.device)
         final = torch.empty(L.STATE_DIM, self.n, dtype=F32, device=self.device) if want_final else None
-        self._call("ag_rollout_forward", _ptr(x0), C.c_int32(int(n_steps)), C.c_int32(int(ckpt_every)),
-                   C.c_float(w_omega), _ptr(ws), C.c_size_t(ws.numel()), _ptr(loss), _ptr(final))
-        return loss, final
+        self._call("ag_rollout_forward", _ptr(x0), _ptr(gains), C.c_int32(int(n_steps)), C.c_int32(int(ckpt_every)),
+                   C.c_float(w_omega), _ptr(ws), C.c_size_t(ws.numel()), _ptr(loss), _ptr(batch), _ptr(final))
+        return loss, batch, final
 
-    def rollout_adjoint(self, n_steps, ckpt_every, w_omega=0.01, seed_grad=1.0, x0=None):
-        ws = self.rollout_workspace(n_steps, ckpt_every)
+    def rollout_adjoint(self, n_steps, ckpt_every, w_omega=0.01, seed_grad=1.0, x0=None, gains=None, ws=None,
+                        seed_dev=None):
+        """dL/dgains [10, n] and dL/dx0 [13, n] times seed_grad (and times the
+        device scalar ``seed_dev`` when given)."""
+        ws = self.rollout_workspace(n_steps, ckpt_every) if ws is None else ws
         dg = torch.empty(L.NGAINS, self.n, dtype=F32, device=self.device)
         dx = torch.empty(L.STATE_DIM, self.n, dtype=F32, device=self.device)
-        self._call("ag_rollout_adjoint", _ptr(x0), C.c_int32(int(n_steps)), C.c_int32(int(ckpt_every)),
-                   C.c_float(w_omega), C.c_float(seed_grad), _ptr(ws), C.c_size_t(ws.numel()), _ptr(dg),
-                   _ptr(dx))
+        self._call("ag_rollout_adjoint", _ptr(x0), _ptr(gains), C.c_int32(int(n_steps)), C.c_int32(int(ckpt_every)),
+                   C.c_float(w_omega), C.c_float(seed_grad), _ptr(seed_dev), _ptr(ws), C.c_size_t(ws.numel()),
+                   _ptr(dg), _ptr(dx))
         return dg, dx

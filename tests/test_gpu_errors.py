@@ -65,10 +65,11 @@ def test_rollout_needs_per_vehicle_parameters_and_workspace():
     need = sim.rollout_workspace(10, 5).numel()
     small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
     loss = torch.empty(sim.n, device="cuda")
-    st = sim._lib.ag_rollout_forward(sim.h, C.c_void_p(0), 10, 5, C.c_float(0.01), C.c_void_p(small.data_ptr()),
-                                     C.c_size_t(small.numel()), C.c_void_p(loss.data_ptr()), C.c_void_p(0))
+    st = sim._lib.ag_rollout_forward(sim.h, C.c_void_p(0), C.c_void_p(0), 10, 5, C.c_float(0.01),
+                                     C.c_void_p(small.data_ptr()), C.c_size_t(small.numel()),
+                                     C.c_void_p(loss.data_ptr()), C.c_void_p(0), C.c_void_p(0))
     assert st == L.AG_E_NOMEM
-    loss2, _ = sim.rollout_forward(10, 5)                 # the handle still works
+    loss2, _, _ = sim.rollout_forward(10, 5)              # the handle still works
     sim.sync()
     assert torch.isfinite(loss2).all()
     sim.close()

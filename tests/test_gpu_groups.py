@@ -96,3 +96,37 @@ def test_full_size_uneven_fleet_sampled_parity():
     dx = (gpu[it, :3] - ref[:, :3]).norm(dim=-1)
     print("full uneven fleet: %d vehicles, sampled position error max %.3e" % (wl.n, dx.max()))
     assert dx.max() <= 1e-4
+
+
+def test_full_size_uneven_fleet_2000_steps_light_and_heavy():
+    """The full 48-group fleet for the configuration's 2,000 steps in the
+    tuned fused launch, against the oracle run one by one on sampled vehicles:
+    random ones, the 20 lightest and 20 heaviest (mass 0.5 and 3 kg ends of the
+    mass-scaled parameters), and the first vehicle of every group.  Closed-loop
+    position control damps the FP32 rounding: positions agree within 1e-4 m
+    and attitudes (rotation matrices) within 1e-4."""
+    need_gpu()
+    from parity import same_rotation_err
+    wl = workloads.c3_uneven()
+    sim = make_sim(wl, autotune_scratch=True)
+    sim.autotune(512)
+    sim.step(wl.steps)
+    sim.sync()
+    gpu = to_vm64(sim.state)
+    sim.close()
+    mass = wl.vparams[0].astype(np.float64)
+    order = np.argsort(mass, kind="stable")
+    rng = np.random.default_rng(1)
+    idx = np.unique(np.concatenate([rng.choice(wl.n, 120, replace=False), order[:20], order[-20:],
+                                    [g.first for g in wl.groups], [wl.n - 1]]))
+    s0, mode, tgt, fleet = oracle_inputs(wl)
+    it = torch.as_tensor(idx)
+    ref, _, _ = oracle.step.rollout(s0[it], mode[it], tgt[it], fleet.select(it), wl.dt, wl.g, wl.steps)
+    dx = (gpu[it, :3] - ref[:, :3]).norm(dim=-1)
+    dR = same_rotation_err(gpu[it, 6:10], ref[:, 6:10])
+    light, heavy = np.isin(idx, order[:20]), np.isin(idx, order[-20:])
+    print("2,000 steps, %d sampled vehicles: position error max %.3e (lightest %.3e, heaviest %.3e), "
+          "attitude max %.3e; masses %.3f..%.3f"
+          % (len(idx), dx.max(), dx[light].max(), dx[heavy].max(), dR.max(), mass[order[0]], mass[order[-1]]))
+    assert light.sum() == 20 and heavy.sum() == 20
+    assert dx.max() <= 1e-4 and dR.max() <= 1e-4

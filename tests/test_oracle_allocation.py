@@ -67,3 +67,34 @@ def test_clamp_bounds_and_hover_split():
     assert torch.equal(u[2, :6], torch.zeros(6, dtype=F64))            # clamped at u_min
     assert torch.equal(u[:, 6:], torch.zeros(3, 2, dtype=F64))
     assert allocation.saturated_count(raw, fleet).tolist() == [0, 6, 6]
+
+
+def test_clamp_distance_closed_form_and_rotor_columns():
+    """Distance of the raw command nearest a clamp bound, relative to u_max:
+    hover split of a 1 kg quad (u = g/4 in [0, 6]) gives min(g/4, 6 - g/4)/6;
+    padding columns past a vehicle's rotor count do not count."""
+    from oracle import Fleet
+    import workloads
+    groups = [workloads.Group(0, 1), workloads.Group(1, 1, n_rotors=6, u_max=5.0)]
+    fleet = Fleet.from_groups(groups, 2, None)
+    raw = torch.full((2, 8), -100.0, dtype=torch.float64)
+    raw[0, :4] = 9.81 / 4
+    raw[1, :6] = torch.tensor([1.0, 2.0, 4.8, 3.0, 2.5, 1.5], dtype=torch.float64)   # 0.2 below u_max
+    d = allocation.clamp_distance(raw, fleet)
+    assert abs(float(d[0]) - min(9.81 / 4, 6 - 9.81 / 4) / 6) < 1e-15
+    assert abs(float(d[1]) - 0.2 / 5.0) < 1e-15
+
+
+def test_clamp_margin_of_a_hovering_rollout():
+    """A hovering quad is a fixed point: every step's raw commands are g/4."""
+    import oracle
+    import workloads
+    from oracle import Fleet
+    fleet = Fleet.from_groups([workloads.Group(0, 3)], 3, None)
+    s0 = torch.zeros(3, 13, dtype=torch.float64)
+    s0[:, 6] = 1.0
+    s0[:, 0:3] = torch.tensor([[0.0, 0.0, 0.0], [1.0, -2.0, 3.0], [0.5, 0.5, -0.5]], dtype=torch.float64)
+    tgt = torch.zeros(3, 4, dtype=torch.float64)
+    tgt[:, 0:3] = s0[:, 0:3]
+    m = oracle.step.clamp_margin(s0, torch.zeros(3, dtype=torch.int64), tgt, fleet, 0.01, 9.81, 30)
+    assert (m - min(9.81 / 4, 6 - 9.81 / 4) / 6).abs().max() < 1e-12

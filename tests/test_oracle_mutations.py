@@ -190,3 +190,16 @@ def test_stats_mistakes_are_caught(monkeypatch):
         monkeypatch.setattr(ostats, "final_state_stats", bad)
         with pytest.raises(AssertionError):
             tts.test_stats_hand_built_state()
+
+
+def test_clamp_distance_against_one_bound_only_is_caught(monkeypatch):
+    def bad(raw, fleet):
+        N = raw.shape[0]
+        d = torch.full((N,), float("inf"), dtype=raw.dtype)
+        for nr in sorted(set(int(k) for k in fleet.n_rotors.tolist())):
+            idx = (fleet.n_rotors == nr).nonzero().squeeze(-1)
+            d[idx] = (raw[idx, :nr] - fleet.u_min[idx, None]).abs().min(-1).values / fleet.u_max[idx]
+        return d
+    monkeypatch.setattr(allocation, "clamp_distance", bad)
+    with pytest.raises(AssertionError):
+        ta.test_clamp_distance_closed_form_and_rotor_columns()
