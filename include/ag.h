@@ -358,6 +358,23 @@ ag_status ag_rollout_adjoint(ag_handle h, const float* x0, const float* gains, i
                              int32_t ckpt_every, float w_omega, float seed_grad, const float* seed_dev,
                              void* ws, size_t ws_bytes, float* dgains, float* dx0);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * forward and adjoint of the differentiable rollout above in one call,
+ * ag_rollout_forward (per-vehicle and batch loss) followed by
+ * ag_rollout_adjoint (seed_grad, no device factor), with the checkpoints,
+ * tapes and loss partials in the library's own static device scratch instead
+ * of a caller workspace.  Allocates nothing.  The scratch holds 192 MiB per
+ * GPU (the 65,536-vehicle, 200-step, 20-step-checkpoint rollout needs 171 MB):
+ * a rollout whose ag_rollout_workspace_size exceeds it is rejected with
+ * AG_E_NOMEM and a message, nothing enqueued.  Every call on one GPU shares
+ * that GPU's scratch (from any handle), so calls that overlap on one GPU
+ * (different streams, threads or handles) race; calls on one stream do not.
+ * Other arguments, outputs and errors as for the two calls it combines. */
+ag_status ag_rollout_grad_noalloc(ag_handle h, const float* x0, const float* gains, int32_t n_steps,
+                                  int32_t ckpt_every, float w_omega, float seed_grad, float* loss_out,
+                                  float* batch_loss, float* dgains, float* dx0);
+
 /* Wait for the handle's stream; returns a sticky error if one occurred. */
 ag_status ag_sync(ag_handle h);
 const char* ag_last_error(ag_handle h);

@@ -23,9 +23,44 @@
 
 using namespace ag;
 
+// Scratch of ag_rollout_grad_noalloc: checkpoints, tapes and loss partials of
+// one differentiable rollout, in the code object's own device memory (each
+// GPU the library is loaded on holds a copy until the process ends).  Host
+// code never uses this name as an address: ag_create looks up each device's
+// copy with hipGetSymbolAddress and keeps that pointer.
+constexpr size_t kNoAllocScratchBytes = (size_t)192 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kRolloutBlock = 64;     // vehicles per block of the rollout kernels
+
+// Device address of `scratch` on each device, looked up once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// With device `dev` current: the address of its copy of `scratch` (null if
+// the lookup failed; *err then says why).
+void* device_scratch(int dev, hipError_t* err) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+        g_scratch_err[dev] = e;
+        g_scratch_done[dev] = true;
+    }
+    *err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
@@ -116,6 +151,8 @@ struct ag_sim {
     int num_cus;
     std::vector<std::pair<long long, int>> span_cache;
     EvBufs ev;
+    void* noalloc_scratch;        // this device's copy of `scratch`, or null
+    hipError_t noalloc_err;       // why the lookup failed
 };
 
 namespace {
@@ -643,6 +680,9 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         h->num_cus = 256;
+    h->noalloc_err = hipSuccess;
+    h->noalloc_scratch = hipGetDevice(&dev) == hipSuccess ? device_scratch(dev, &h->noalloc_err) : nullptr;
+    if (!h->noalloc_scratch && h->noalloc_err == hipSuccess) h->noalloc_err = hipErrorInvalidDevice;
     h->exec = {1, 256, 1, 16, 0, h->stream != nullptr ? 1 : 0};
 
     std::vector<float> tab((size_t)cfg->n_groups * GSTRIDE);
@@ -655,6 +695,7 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
         h->goff_host[g] = (int32_t)h->groups[g].first;
     }
     h->goff_host[cfg->n_groups] = (int32_t)cfg->n;
+    tile_span(h, kRolloutBlock);   // cached now: rollout calls then allocate no host memory
     StatAcc zero{};
     hipError_t e = hipMemcpyAsync(h->gtab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
@@ -1217,8 +1258,6 @@ ag_status ag_rollout_workspace_size(ag_handle h, int32_t n_steps, int32_t ckpt_e
 
 namespace {
 
-constexpr int kRolloutBlock = 64;
-
 ag_status rollout_args(ag_handle h, const float* x0, const float* gains, int32_t n_steps, int32_t ckpt_every,
                        float w_omega, void* ws, size_t ws_bytes, RolloutArgs& a, LaunchShape& s) {
     if (n_steps < 1 || ckpt_every < 1) return set_err(h, AG_E_INVALID, "n_steps and ckpt_every must be >= 1");
@@ -1301,6 +1340,29 @@ ag_status ag_rollout_adjoint(ag_handle h, const float* x0, const float* gains, i
     a.seed_dev = seed_dev;
     // two wavefronts per 64 vehicles: reverse sweep and recomputation
     return launch(h, rollout_adj_kernel(h->nr_class), s.grid, dim3(2 * kRolloutBlock), s.shmem, &a);
+}
+
+ag_status ag_rollout_grad_noalloc(ag_handle h, const float* x0, const float* gains, int32_t n_steps,
+                                  int32_t ckpt_every, float w_omega, float seed_grad, float* loss_out,
+                                  float* batch_loss, float* dgains, float* dx0) {
+    AG_CHECK_HANDLE(h);
+    if (!h->noalloc_scratch)
+        return hip_fail(h, h->noalloc_err, "ag_rollout_grad_noalloc: device address of the static scratch");
+    size_t need = 0;
+    ag_status st = ag_rollout_workspace_size(h, n_steps, ckpt_every, &need);
+    if (st != AG_OK) return set_err(h, st, "n_steps and ckpt_every must be >= 1");
+    if (need > kNoAllocScratchBytes) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg,
+                      "ag_rollout_grad_noalloc: the rollout needs %zu bytes of scratch, the static scratch holds %zu",
+                      need, kNoAllocScratchBytes);
+        return set_err(h, AG_E_NOMEM, msg);
+    }
+    st = ag_rollout_forward(h, x0, gains, n_steps, ckpt_every, w_omega, h->noalloc_scratch, kNoAllocScratchBytes,
+                            loss_out, batch_loss, nullptr);
+    if (st != AG_OK) return st;
+    return ag_rollout_adjoint(h, x0, gains, n_steps, ckpt_every, w_omega, seed_grad, nullptr, h->noalloc_scratch,
+                              kNoAllocScratchBytes, dgains, dx0);
 }
 
 ag_status ag_sync(ag_handle h) {

@@ -11,7 +11,7 @@ FLAG_NONFINITE, FLAG_SATURATED, FLAG_RESET = 1, 2, 4
 EXPORTS = [
     "ag_workspace_size", "ag_create", "ag_destroy", "ag_set_targets", "ag_step", "ag_prepare", "ag_set_exec",
     "ag_get_exec", "ag_autotune", "ag_reset", "ag_randomize_obstacles", "ag_render_depth", "ag_apply_actions", "ag_observe", "ag_get_stats", "ag_get_step", "ag_set_step",
-    "ag_rollout_workspace_size", "ag_rollout_forward", "ag_rollout_adjoint", "ag_sync",
+    "ag_rollout_workspace_size", "ag_rollout_forward", "ag_rollout_adjoint", "ag_rollout_grad_noalloc", "ag_sync",
     "ag_last_error", "ag_status_string",
 ]
 
@@ -93,6 +93,7 @@ def load():
         "ag_rollout_forward": ([H, P, P, C.c_int32, C.c_int32, C.c_float, P, C.c_size_t, P, P, P], C.c_int),
         "ag_rollout_adjoint": ([H, P, P, C.c_int32, C.c_int32, C.c_float, C.c_float, P, P, C.c_size_t, P, P],
                                C.c_int),
+        "ag_rollout_grad_noalloc": ([H, P, P, C.c_int32, C.c_int32, C.c_float, C.c_float, P, P, P, P], C.c_int),
         "ag_sync": ([H], C.c_int),
         "ag_last_error": ([H], C.c_char_p),
         "ag_status_string": ([C.c_int], C.c_char_p),

@@ -304,3 +304,18 @@ class Sim:
                    C.c_float(w_omega), C.c_float(seed_grad), _ptr(seed_dev), _ptr(ws), C.c_size_t(ws.numel()),
                    _ptr(dg), _ptr(dx))
         return dg, dx
+
+    def rollout_grad_noalloc(self, n_steps, ckpt_every, w_omega=0.01, seed_grad=1.0, x0=None, gains=None,
+                             out=None):
+        """Forward and adjoint in one call on the library's static scratch (no
+        device allocation by the library).  ``out``: optional preallocated
+        (loss [n], batch [1], dgains [10, n], dx0 [13, n]) tensors."""
+        if out is None:
+            out = (torch.empty(self.n, dtype=F32, device=self.device), torch.empty(1, dtype=F32, device=self.device),
+                   torch.empty(L.NGAINS, self.n, dtype=F32, device=self.device),
+                   torch.empty(L.STATE_DIM, self.n, dtype=F32, device=self.device))
+        loss, batch, dg, dx = out
+        self._call("ag_rollout_grad_noalloc", _ptr(x0), _ptr(gains), C.c_int32(int(n_steps)),
+                   C.c_int32(int(ckpt_every)), C.c_float(w_omega), C.c_float(seed_grad), _ptr(loss), _ptr(batch),
+                   _ptr(dg), _ptr(dx))
+        return loss, batch, dg, dx
