@@ -346,10 +346,6 @@ int tile_span(ag_handle h, long long tile) {
 
 size_t lds_bytes(int span) { return (size_t)span * GSTRIDE * sizeof(float) + (size_t)(span + 1) * sizeof(int32_t); }
 
-// Byte offset of the prefetch buffer of pipelined launches: after the group
-// entries and offsets, rounded up to 16 bytes (the kernel's layout).
-size_t pf_offset_bytes(int span) { return (((size_t)span * GSTRIDE + span + 1 + 3) & ~(size_t)3) * 4; }
-
 StepArgs base_args(ag_handle h) {
     StepArgs a{};
     a.state = h->cfg.state;
@@ -460,18 +456,13 @@ std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
     const bool trk = h->cfg.traj != nullptr;
     if (trk && vpl != 1) return "with a trajectory buffer exec.vpl must be 1";
     const bool events = h->reset_on && !one && h->ev.cap > 0;
-    // a persistent fused grid (fewer blocks than tiles) copies each block's
-    // next tile into LDS while it steps the current one
-    const bool pf = !one && vpl == 1 && !h->reset_on && !trk && grid < ntiles;
-    s.fn = step_kernel(h->nr_class, h->vp, events ? 2 : (h->reset_on ? 1 : 0), vpl, one, obs, trk, pf);
-    s.fn_fb = events ? step_kernel(h->nr_class, h->vp, 1, vpl, one, obs, trk, false) : nullptr;
+    s.fn = step_kernel(h->nr_class, h->vp, events ? 2 : (h->reset_on ? 1 : 0), vpl, one, obs, trk);
+    s.fn_fb = events ? step_kernel(h->nr_class, h->vp, 1, vpl, one, obs, trk) : nullptr;
     if (!s.fn || (events && !s.fn_fb)) return "no kernel for this combination of policy and configuration";
     s.grid = dim3((unsigned)grid);
     s.block = dim3((unsigned)e.block);
     s.span = span;
     s.shmem = lds_bytes(span);
-    if (pf) s.shmem = pf_offset_bytes(span) + (size_t)pf_rows_of(h->vp) * e.block * sizeof(float);
-    if (s.shmem > 160 * 1024) return "tile needs more LDS than a CU has (smaller block or fewer groups per tile)";
     return "";
 }
 
@@ -989,14 +980,8 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
                     LaunchShape s;
                     if (!shape_for(h, cand, s).empty()) continue;
                     if (gmode == 1) {
-                        // a persistent grid: as many blocks as fit on the chip at
-                        // once, with the kernel such a grid launches (pipelined
-                        // for one vehicle per lane, which needs more LDS)
-                        LaunchShape sp;
-                        ag_exec probe_grid = cand;
-                        probe_grid.grid = 1;
-                        if (!shape_for(h, probe_grid, sp).empty() || !sp.fn) continue;
-                        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_blocks_per_cu, sp.fn, b, sp.shmem) !=
+                        // a persistent grid: as many blocks as fit on the chip at once
+                        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_blocks_per_cu, s.fn, b, s.shmem) !=
                                 hipSuccess || occ_blocks_per_cu < 1)
                             continue;
                         long long gp = (long long)h->num_cus * occ_blocks_per_cu;

@@ -119,12 +119,7 @@ constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
 // past the buffer itself); 2 fused launch whose events all fit the buffer.
 // A fused launch with resets runs the rst = 2 and rst = 1 kernels in turn;
 // each leaves at once unless the launch's event count selects it.
-// pf: the pipelined persistent form (fused, one vehicle per lane, no resets
-// or trajectories, grid smaller than the tile count), whose dynamic LDS holds
-// pf_rows_of(vp) rows of block floats after the group entries and offsets
-// (16-byte aligned); null where no such kernel exists.
-const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk, bool pf);
-int pf_rows_of(bool vp);
+const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk);
 const void* fold_kernel();
 const void* advance_kernel();
 const void* set_step_kernel();

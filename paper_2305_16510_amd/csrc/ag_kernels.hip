@@ -111,16 +111,8 @@ constexpr bool spec_loops(bool one, int vpl, bool obs, bool trk, int rst) {
 // The tiles of one block.  UNI (per-step kernels of a single-group launch):
 // the one group entry is loaded ahead of the state and written to LDS
 // without the group search and its extra barrier.
-// Rows a pipelined launch copies per vehicle into LDS ahead of its tile:
-// state (13), command (4) and, with per-vehicle parameters, their 16 rows.
-constexpr int pf_rows(bool vp) { return 17 + (vp ? 16 : 0); }
-
-// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
-constexpr int kWaitVm0 = 0x0F70;     // every vector memory access done
-constexpr int kWaitLgkm0 = 0xC07F;   // every LDS access done
-
-template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK, bool UNI, bool PF>
-__device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* loff, int* sh, float* pfb) {
+template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK, bool UNI>
+__device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* loff, int* sh) {
     // RST: 0 no resets; 1 resets (per-step form: found and redrawn here; fused
     // form: from the event kernels, events past the buffer redrawn here); 2
     // fused form with every event of the launch in the buffer (no redraw code)
@@ -140,37 +132,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
     long long c_sat = 0, c_res = 0, c_nonf = 0, c_fin = 0, c_pos = 0;
     double s_err = 0.0, s_w = 0.0;
 
-    // PF (pipelined persistent launches, one vehicle per lane): the rows of
-    // the block's current tile are in LDS (pfb[r * B + lane], put there by
-    // direct global-to-LDS loads issued during the previous tile), and so are
-    // the lane's vehicle index and mode in registers.  Each wavefront copies
-    // and reads only its own 64 columns, so no barrier guards the buffer.
-    int pf_il = 0, pf_il_next = 0, pf_il_after = 0;   // vehicle indices (n < 2^31)
-    int pf_md = 0, pf_md_next = 0;
-    float* const pf_wave = pfb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
-    // issue the copies of vehicle il's rows (this lane's column of the next tile)
-    auto prefetch = [&](const int il) {
-#pragma unroll
-        for (int r = 0; r < 13; ++r) __builtin_amdgcn_global_load_lds(a.state + r * ld + il, pf_wave + r * B, 4, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            __builtin_amdgcn_global_load_lds(a.target + r * ld + il, pf_wave + (13 + r) * B, 4, 0, 0);
-        if constexpr (VP) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                __builtin_amdgcn_global_load_lds(a.vparams + r * ld + il, pf_wave + (17 + r) * B, 4, 0, 0);
-        }
-        pf_md_next = (int)a.mode[il];
-    };
-    // vehicle index of this lane in tile t (positions past n take vehicle n - 1)
-    auto lane_vehicle = [&](const long long t) -> int {
-        const long long p = t * TILE + threadIdx.x;
-        const int pl = (int)(p < a.n ? p : a.n - 1);
-        return (SPEC && a.perm) ? a.perm[pl] : pl;
-    };
-
-    // next, after: the block's next two tiles (-1: none), for PF
-    auto tile_body = [&](const long long base, const long long next, const long long after) {
+    auto tile_body = [&](const long long base) {
         const long long end = base + TILE < a.n ? base + TILE : a.n;
         float s[VPL][13];
         float tg[VPL][4];
@@ -204,27 +166,18 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             act[v] = p < a.n;
             sat_last[v] = 0;
             did_reset[v] = false;
-            if constexpr (PF) {
-                idx[v] = SPEC ? (long long)pf_il : p;
+            const long long pl = act[v] ? p : a.n - 1;
+            // with a mode order, lane position p steps vehicle perm[p] (same
+            // group as vehicle p, so the staged table entries still apply)
+            const long long il = (SPEC && a.perm) ? (long long)a.perm[pl] : pl;
+            // (the other kernels store through the unclamped position, so the
+            // compiler does not keep the load addresses live for the stores)
+            idx[v] = SPEC ? il : p;
 #pragma unroll
-                for (int r = 0; r < 13; ++r) s[v][r] = pfb[r * B + threadIdx.x];
-                md[v] = pf_md;
+            for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + il];
+            md[v] = (int)a.mode[il];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) tg[v][r] = pfb[(13 + r) * B + threadIdx.x];
-            } else {
-                const long long pl = act[v] ? p : a.n - 1;
-                // with a mode order, lane position p steps vehicle perm[p] (same
-                // group as vehicle p, so the staged table entries still apply)
-                const long long il = (SPEC && a.perm) ? (long long)a.perm[pl] : pl;
-                // (the other kernels store through the unclamped position, so the
-                // compiler does not keep the load addresses live for the stores)
-                idx[v] = SPEC ? il : p;
-#pragma unroll
-                for (int r = 0; r < 13; ++r) s[v][r] = a.state[r * ld + il];
-                md[v] = (int)a.mode[il];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + il];
-            }
+            for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + il];
         }
         // fused launches with resets: this launch's reset events of each lane
         // (bit mask over the k steps, first event index) and the first
@@ -255,18 +208,10 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             if (act[v]) {
                 const long long i = idx[v];
                 gt[v] = UNI ? lds : lane_group(lds, loff, cnt, i);
-                if constexpr (PF) load_params<VP>(P[v], gt[v], pfb + 17 * B, B, threadIdx.x);
-                else load_params<VP>(P[v], gt[v], a.vparams, ld, i);
+                load_params<VP>(P[v], gt[v], a.vparams, ld, i);
                 derive_cmd(C[v], md[v], tg[v][0], tg[v][1], tg[v][2], tg[v][3]);
                 if constexpr (TRK) derive_traj(C[v], a.traj, ld, i);
             }
-        }
-        if constexpr (PF) {
-            // the buffer is read: copy the next tile's rows into it while this
-            // tile is stepped, and fetch the lane's vehicle in the tile after
-            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-            if (next >= 0) prefetch(pf_il_next);
-            if (after >= 0) pf_il_after = lane_vehicle(after);
         }
 
         Wrench W[VPL];
@@ -363,10 +308,6 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             for (int st = 0; st < k_loop; ++st) run_step(st, std::false_type{}, General{});
         }
         if (want_out) run_step(K - 1, std::true_type{}, General{});
-        // PF: the next tile's copies (issued before the step loop) are done
-        // before this tile's stores, so the next tile reads its buffer and its
-        // mode register without waiting
-        if constexpr (PF) __builtin_amdgcn_s_waitcnt(kWaitVm0);
 
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
@@ -430,42 +371,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
         // a per-step launch has one block per tile (its grid is the tile count),
         // and no loop: nothing written by the block precedes its table reads
         const long long base = (long long)blockIdx.x * TILE;
-        if (base < a.n) tile_body(base, -1, -1);
-    } else if constexpr (PF) {
-        // persistent grid: block b steps tiles b, b + G, b + 2G, ...; in mode
-        // order with G a multiple of 8, the blocks of XCD x (b mod 8 = x) share
-        // one contiguous eighth of the tiles instead (their mode runs then
-        // meet in that XCD's L2)
-        const long long ntiles = (a.n + TILE - 1) / TILE;
-        const long long G = gridDim.x, b = blockIdx.x;
-        const bool xcd = SPEC && NR != 0 && a.perm && (G & 7) == 0;
-        long long first, stride, last;      // tiles first, first + stride, ... < last
-        if (xcd) {
-            const long long x = b & 7, per = ntiles >> 3, rem = ntiles & 7;
-            const long long start = x * per + (x < rem ? x : rem);
-            first = start + (b >> 3);
-            stride = G >> 3;
-            last = start + per + (x < rem ? 1 : 0);
-        } else {
-            first = b;
-            stride = G;
-            last = ntiles;
-        }
-        auto tile_at = [&](const long long t) { return t < last ? t : -1ll; };
-        if (first < last) {
-            // prologue: the first tile's rows, and the lane's vehicle in the second
-            pf_il = lane_vehicle(first);
-            prefetch(pf_il);
-            pf_il_next = tile_at(first + stride) >= 0 ? lane_vehicle(first + stride) : 0;
-            __builtin_amdgcn_s_waitcnt(kWaitVm0);
-            pf_md = pf_md_next;
-            for (long long t = first; t < last; t += stride) {
-                tile_body(t * TILE, tile_at(t + stride), tile_at(t + 2 * stride));
-                pf_il = pf_il_next;
-                pf_md = pf_md_next;
-                pf_il_next = pf_il_after;
-            }
-        }
+        if (base < a.n) tile_body(base);
     } else {
         const long long ntiles = (a.n + TILE - 1) / TILE;
         if (SPEC && NR != 0 && a.perm && (long long)gridDim.x == ntiles) {
@@ -477,9 +383,9 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             // rotor counts: their groups would load the XCDs unevenly.)
             const long long i = blockIdx.x, x = i & 7, j = i >> 3;
             const long long per = ntiles >> 3, rem = ntiles & 7;
-            tile_body((x * per + (x < rem ? x : rem) + j) * TILE, -1, -1);
+            tile_body((x * per + (x < rem ? x : rem) + j) * TILE);
         } else {
-            for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile * TILE, -1, -1);
+            for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) tile_body(tile * TILE);
         }
     }
     if constexpr (OBS) {
@@ -487,14 +393,12 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
     }
 }
 
-template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK, bool PF = false>
+template <int NR, bool VP, int RST, int VPL, bool ONE, bool OBS, bool TRK>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VPL == 1 && !TRK && ((RST == 2 && !OBS) || spec_loops(ONE, VPL, OBS, TRK, RST)) ? (RST == 2 && OBS ? 3 : 4) : 1)))
 void k_step(StepArgs a) {
     extern __shared__ float4 lds4[];
     float* lds = reinterpret_cast<float*>(lds4);
     int* loff = reinterpret_cast<int*>(lds + a.span * GSTRIDE);
-    // PF: the prefetch buffer follows the group entries and offsets (16-byte aligned)
-    float* pfb = lds + ((a.span * GSTRIDE + a.span + 1 + 3) & ~3);
     __shared__ int sh[2];
     if constexpr (RST != 0 && !ONE) {
         // both event variants are launched; the one that does not match the
@@ -504,11 +408,11 @@ void k_step(StepArgs a) {
     }
     if constexpr (ONE) {
         if (a.n_groups == 1) {     // uniform across the grid
-            step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, true, false>(a, lds, loff, sh, pfb);
+            step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, true>(a, lds, loff, sh);
             return;
         }
     }
-    step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, false, PF>(a, lds, loff, sh, pfb);
+    step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, false>(a, lds, loff, sh);
 }
 
 // ---- statistics fold: slots -> cumulative accumulator (one block) ---------
@@ -974,53 +878,45 @@ const void* observe_kernel() { return reinterpret_cast<const void*>(&k_observe);
 // ---- kernel lookup ---------------------------------------------------------
 // Kernels with trajectories (mode 4) exist for one vehicle per lane and for
 // the quad and mixed rotor classes only.
-// Pipelined kernels exist for fused one-vehicle-per-lane launches without
-// resets or trajectories.
 template <int NR, bool VP, int RST, bool OBS, bool TRK>
-static const void* pick_shape(int vpl, bool one, bool pf) {
+static const void* pick_shape(int vpl, bool one) {
     if constexpr (RST != 2) {
         if (one) return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 1, true, OBS, TRK>);
     }
     if constexpr (!TRK) {
         if (vpl == 2) return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 2, false, OBS, TRK>);
     }
-    if constexpr (RST == 0 && !TRK) {
-        if (pf) return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 1, false, OBS, TRK, true>);
-    }
     return reinterpret_cast<const void*>(&k_step<NR, VP, RST, 1, false, OBS, TRK>);
 }
 
 template <int NR, bool VP, int RST, bool TRK>
-static const void* pick_obs(int vpl, bool one, bool obs, bool pf) {
-    return obs ? pick_shape<NR, VP, RST, true, TRK>(vpl, one, pf) : pick_shape<NR, VP, RST, false, TRK>(vpl, one, pf);
+static const void* pick_obs(int vpl, bool one, bool obs) {
+    return obs ? pick_shape<NR, VP, RST, true, TRK>(vpl, one) : pick_shape<NR, VP, RST, false, TRK>(vpl, one);
 }
 
 template <int NR, bool VP, bool TRK>
-static const void* pick_rst(int rst, int vpl, bool one, bool obs, bool pf) {
-    if (rst == 2) return pick_obs<NR, VP, 2, TRK>(vpl, one, obs, pf);
-    if (rst == 1) return pick_obs<NR, VP, 1, TRK>(vpl, one, obs, pf);
-    return pick_obs<NR, VP, 0, TRK>(vpl, one, obs, pf);
+static const void* pick_rst(int rst, int vpl, bool one, bool obs) {
+    if (rst == 2) return pick_obs<NR, VP, 2, TRK>(vpl, one, obs);
+    if (rst == 1) return pick_obs<NR, VP, 1, TRK>(vpl, one, obs);
+    return pick_obs<NR, VP, 0, TRK>(vpl, one, obs);
 }
 
 template <int NR, bool TRK>
-static const void* pick_nr(bool vp, int rst, int vpl, bool one, bool obs, bool pf) {
-    return vp ? pick_rst<NR, true, TRK>(rst, vpl, one, obs, pf) : pick_rst<NR, false, TRK>(rst, vpl, one, obs, pf);
+static const void* pick_nr(bool vp, int rst, int vpl, bool one, bool obs) {
+    return vp ? pick_rst<NR, true, TRK>(rst, vpl, one, obs) : pick_rst<NR, false, TRK>(rst, vpl, one, obs);
 }
 
-const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk, bool pf) {
+const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk) {
     if (rst == 2 && one_step) return nullptr;
-    if (pf && (one_step || vpl != 1 || rst != 0 || trk)) return nullptr;
-    if (trk) return nr_class == 4 ? pick_nr<4, true>(vp, rst, vpl, one_step, obs, false)
-                                  : pick_nr<0, true>(vp, rst, vpl, one_step, obs, false);
+    if (trk) return nr_class == 4 ? pick_nr<4, true>(vp, rst, vpl, one_step, obs)
+                                  : pick_nr<0, true>(vp, rst, vpl, one_step, obs);
     switch (nr_class) {
-        case 4: return pick_nr<4, false>(vp, rst, vpl, one_step, obs, pf);
-        case 6: return pick_nr<6, false>(vp, rst, vpl, one_step, obs, pf);
-        case 8: return pick_nr<8, false>(vp, rst, vpl, one_step, obs, pf);
-        default: return pick_nr<0, false>(vp, rst, vpl, one_step, obs, pf);
+        case 4: return pick_nr<4, false>(vp, rst, vpl, one_step, obs);
+        case 6: return pick_nr<6, false>(vp, rst, vpl, one_step, obs);
+        case 8: return pick_nr<8, false>(vp, rst, vpl, one_step, obs);
+        default: return pick_nr<0, false>(vp, rst, vpl, one_step, obs);
     }
 }
-
-int pf_rows_of(bool vp) { return pf_rows(vp); }
 
 const void* fold_kernel() { return reinterpret_cast<const void*>(&k_fold); }
 const void* advance_kernel() { return reinterpret_cast<const void*>(&k_advance); }

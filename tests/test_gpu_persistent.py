@@ -1,11 +1,9 @@
-"""Persistent fused launches (fewer blocks than tiles) copy each block's next
-tile from HBM into LDS while they step the current one.  These tests check
-that this changes no bit of any vehicle's trajectory against plain per-step
-launches: mixed command modes in mode order (grids that are multiples of 8
-deal contiguous tile ranges to each XCD, others stride over the tiles), calls
-too short for the order, per-vehicle parameters over uneven groups with all
-three rotor layouts, observers (wrench and rotor outputs, flags, statistics),
-a ragged last tile and XCDs with few tiles per block."""
+"""Persistent fused launches (fewer blocks than tiles: each block strides over
+the tiles) against plain per-step launches, bitwise: mixed command modes in
+mode order, calls too short for the order, per-vehicle parameters over
+uneven groups with all three rotor layouts, a single rotor class with
+per-vehicle parameters, observers (wrench and rotor outputs, flags,
+statistics), a ragged last tile and few tiles per block."""
 import numpy as np
 import pytest
 import torch
@@ -83,7 +81,7 @@ def test_observers_and_statistics():
 
 
 def test_few_tiles_per_xcd():
-    """79 tiles over 72 blocks: each XCD's nine blocks share nine or ten tiles."""
+    """79 tiles over 72 blocks: most blocks step one tile, seven step two."""
     need_gpu()
     wl = workloads.c2_scale(n=5_000, seed=76)             # 79 tiles of 64
     ref, _ = run(wl, PLAIN, [40])
