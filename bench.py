@@ -49,28 +49,58 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the
 # 1,048,576-quad workload, scaled by what the same counters read for a plain
-# 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), and VALU instructions per
-# vehicle-step of the fused kernel (SQ_INSTS_VALU / SQ_WAVES / steps).  Valid
-# only while the step-kernel sources hash to ``src``.
+# 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): per-step kernel, and a
+# fused launch (one load and one store of the state per launch, whatever k);
+# VALU instructions per vehicle-step of the fused kernel (SQ_INSTS_VALU /
+# SQ_WAVES / steps) for 20-step and 1,024-step launches.  Valid only while
+# the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "03749f53ff77900e",
-    "per_step_bytes": 127014519.5,
-    "fused_bytes": 134596098.3,
-    "fused_valu_per_vstep": 143.3,
-    "profile": "profiles/step_kernels_1M_quads_mixed_modes.md",
+    "src": "c412a8e1976df2bf",
+    "per_step_bytes": 126992589.0,
+    "fused_bytes": 132265882.0,
+    "fused_valu_per_vstep": {20: 161.5, 1024: 139.9},
+    "per_step_4M_bytes": 508686336.0,
+    "profile": "profiles/fused_step_1M_quads.md",
 }
+
+
+def valu_per_vstep(steps_per_launch):
+    """Counted VALU instructions per vehicle-step for launches of this many
+    steps (the per-launch set-up spreads over fewer steps in short launches:
+    the 20-step figure below 64 steps, the 1,024-step figure from there)."""
+    v = COUNTERS["fused_valu_per_vstep"]
+    return v[20] if steps_per_launch < 64 else v[1024]
+
+
+# The same for the rollout kernels of the 65,536-quad differentiation leg
+# (200 steps per call): VALU instructions per vehicle-step (forward; adjoint
+# counting its reverse and recompute wavefronts) and bytes per call.
+ROLLOUT_COUNTERS = {
+    "fwd_valu_per_vstep": 157.3,
+    "adj_valu_per_vstep": 641.4,
+    "fwd_bytes": 43072184.0,
+    "adj_bytes": 1405685760.0,
+    "profile": "profiles/rollout_65536_quads.md",
+}
+ROLLOUT_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_rollout.hip",
+                   "paper_2305_16510_amd/csrc/ag_internal.h")
+ROLLOUT_SRC = "12c60b2535ea71d1"
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
                 "paper_2305_16510_amd/csrc/ag_internal.h")
 PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090
 
 
-def step_source_hash():
+def step_source_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for p in STEP_SOURCES:
+    for p in sources or STEP_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def rollout_counters_valid():
+    return ROLLOUT_SRC == step_source_hash(ROLLOUT_SOURCES)
 
 
 def counters_valid():
@@ -196,10 +226,21 @@ def bench_adjoint(sync, reps=3):
     sim.close()
     f, a = min(tf), min(ta)
     log(f"adjoint: forward {f * 1e3:.3f} ms, adjoint {a * 1e3:.3f} ms for {T} steps of {wl.n} vehicles")
-    return {"workload": "65,536 quads, 200-step position rollout, checkpoint every 20, 10 gain + 13 state "
-                        "gradients per vehicle", "n_vehicles": wl.n, "steps": T,
-            "forward_s_per_step": f / T, "adjoint_s_per_step": a / T, "fwd_plus_adj_s_per_step": (f + a) / T,
-            "vehicle_steps_per_s_fwd_adj": wl.n * T / (f + a)}
+    out = {"workload": "65,536 quads, 200-step position rollout, checkpoint every 20, 10 gain + 13 state "
+                       "gradients per vehicle", "n_vehicles": wl.n, "steps": T,
+           "forward_s_per_step": f / T, "adjoint_s_per_step": a / T, "fwd_plus_adj_s_per_step": (f + a) / T,
+           "vehicle_steps_per_s_fwd_adj": wl.n * T / (f + a)}
+    if rollout_counters_valid():
+        # VALU issue against the chip's peak issue rate, and bytes moved per
+        # second (the adjoint writes and reads back a 13-float state per
+        # vehicle-step through its tape)
+        peak_issue = FP32_PEAK_TFLOPS * 1e12 / 2
+        rc = ROLLOUT_COUNTERS
+        out["forward_valu_issue_frac_of_peak"] = rc["fwd_valu_per_vstep"] * wl.n * T / f / peak_issue
+        out["adjoint_valu_issue_frac_of_peak"] = rc["adj_valu_per_vstep"] * wl.n * T / a / peak_issue
+        out["adjoint_traffic_GBs"] = rc["adj_bytes"] / a / 1e9
+        out["counters"] = rc["profile"]
+    return out
 
 
 def bench_uneven(sync):
@@ -294,7 +335,10 @@ def bench_per_step_large(sync, steps=200):
             "n_vehicles": wl.n, "steps": steps, "block": blk, "kernel_avg_us": t / steps * 1e6,
             "value": wl.n * steps / t,
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": gbs / HBM_PEAK_GBS}}
+                         "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": COUNTERS["per_step_4M_bytes"] if counters_valid() else None,
+                         "algorithmic_bytes": BYTES_PER_VSTEP * wl.n,
+                         "note": "507 MB per launch, twice the 256 MB Infinity Cache: the bytes come from HBM"}}
 
 
 def bench_camera(sync, n=1024, n_obs=20, W=480, H=270, reps=5):
@@ -427,7 +471,12 @@ def main():
     t_fix = min(event_time(sim.stream, lambda: sim.raw_step(fixed_steps)) for _ in range(3))
     fix_launches = math.ceil(fixed_steps / k_fixed)
     fix_tflops = FLOPS_PER_VSTEP * wl.n * fixed_steps / t_fix / 1e12
-    roofline_fixed = {"steps": fixed_steps, "exec": tuned_fixed, "launches": fix_launches,
+    fix_valu = valu_per_vstep(min(fixed_steps, k_fixed))
+    roofline_fixed = {"valu_instr_per_vehicle_step": fix_valu if counters_valid() else None,
+                      "valu_issue_frac_of_peak": (fix_valu * wl.n * fixed_steps / t_fix) / (FP32_PEAK_TFLOPS * 1e12 / 2)
+                      if counters_valid() else None,
+                      "traffic": COUNTERS["fused_bytes"] if counters_valid() else None,
+                      "steps": fixed_steps, "exec": tuned_fixed, "launches": fix_launches,
                       "steps_per_launch": min(fixed_steps, k_fixed),
                       "kernel_avg_us": t_fix / fix_launches * 1e6, "us_per_step": t_fix / fixed_steps * 1e6,
                       "value": wl.n * fixed_steps / t_fix, "achieved": fix_tflops, "unit": "TFLOP/s",
@@ -476,7 +525,8 @@ def main():
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": gbs / HBM_PEAK_GBS,
                          "traffic": COUNTERS["per_step_bytes"] if counters_valid() else None,
-                         "algorithmic_bytes": BYTES_PER_VSTEP * wl.n},
+                         "algorithmic_bytes": BYTES_PER_VSTEP * wl.n,
+                         "note": "127 MB per launch fits the 256 MB Infinity Cache; per_step_4M is the HBM figure"},
         }
         log(f"per-step: {t_plain * 1e3:.2f} ms -> {per_step['value']:.3e} vehicle-steps/s, "
             f"kernel {kern_plain * 1e6:.1f} us = {gbs:.0f} GB/s; as host calls {t_calls * 1e3:.2f} ms")
@@ -489,8 +539,8 @@ def main():
     valid = counters_valid()
     # VALU utilisation: lane-instructions issued per second against the chip's
     # peak issue rate (157.3 TFLOP/s = 78.6e12 single-lane FMAs per second)
-    valu_util = (COUNTERS["fused_valu_per_vstep"] * wl.n * K / t_evt["fused"]) / (FP32_PEAK_TFLOPS * 1e12 / 2) \
-        if valid else None
+    valu_vstep = valu_per_vstep(min(K, k))
+    valu_util = (valu_vstep * wl.n * K / t_evt["fused"]) / (FP32_PEAK_TFLOPS * 1e12 / 2) if valid else None
     out = {
         "metric": "vehicle-steps/s at 1M quads (fused vs per-step), %HBM/VALU peak; adjoint s/step",
         "value": value,
@@ -518,7 +568,7 @@ def main():
                      "counted": {"flops_per_vehicle_step": fl_count, "achieved": tflops_count,
                                  "frac": tflops_count / FP32_PEAK_TFLOPS,
                                  "what": "per-mode operation count of the fleet's modes (not the headline)"},
-                     "valu_instr_per_vehicle_step": COUNTERS["fused_valu_per_vstep"] if valid else None,
+                     "valu_instr_per_vehicle_step": valu_vstep if valid else None,
                      "valu_issue_frac_of_peak": valu_util,
                      "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},
         "roofline_fixed_shape": roofline_fixed,
@@ -567,7 +617,7 @@ def main():
         out["roofline"]["frac_of_measured_peak"] = out["roofline"]["achieved"] / (2 * fma / 1e12)
         if valid:
             # VALU issue rate against the rate a pure-FMA probe kernel reaches
-            issue = COUNTERS["fused_valu_per_vstep"] * wl.n * K / t_evt["fused"]
+            issue = valu_vstep * wl.n * K / t_evt["fused"]
             out["roofline"]["valu_issue_frac_of_measured"] = issue / fma
         if per_step:
             per_step["roofline"]["frac_of_measured_copy"] = per_step["roofline"]["achieved"] / (cbw / 1e9)
