@@ -13,7 +13,7 @@ Follows Sec. IV of the paper (after Lee et al., 2011) equation by equation:
   machinery, referenced to the commanded yaw psi_d with zero yaw rate;
 * wrench mode (a test mode): (f, M) given directly.
 
-Readings (numbered as in ``readings.py``): z-up inertial frame, gravity
+Readings (numbered as in the package docstring): z-up inertial frame, gravity
 -g e3, thrust +f b3 (R1); eq. (7) read as F = m (a_d + g e3) (R2) and eqs.
 (8)-(9) evaluated on that gravity-compensated F expressed in V (R3); f is the
 projection of F on the current b3 expressed in V (R4); yaw is the Z-Y-X yaw
