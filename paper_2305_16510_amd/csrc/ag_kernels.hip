@@ -592,10 +592,6 @@ __global__ __launch_bounds__(kResetBlock) void k_ev_mask(StepArgs a) {
     }
 }
 
-// Exclusive scan of the per-block event counts in place and their total (one
-// block, fixed order, 64-bit: totals may exceed 2^31).  Each thread sums a
-// contiguous run of counts, one block-wide scan combines the runs, and each
-// thread writes its run's offsets.
 // ---- mode order of fused launches -------------------------------------------
 // One block per segment of kOrderSeg vehicles.  Each piece of the segment that
 // lies in one group is partitioned stably by mode bucket (0, 1, 2, other):
@@ -697,6 +693,10 @@ __global__ __launch_bounds__(kOrderBlock) void k_mode_order(OrderArgs a) {
     }
 }
 
+// Exclusive scan of the per-block event counts in place and their total (one
+// block, fixed order, 64-bit: totals may exceed 2^31).  Each thread sums a
+// contiguous run of counts, one block-wide scan combines the runs, and each
+// thread writes its run's offsets.
 __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
     __shared__ long long buf[1024];
     const int nblocks = (int)((a.n + kResetBlock - 1) / kResetBlock);

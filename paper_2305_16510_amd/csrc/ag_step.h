@@ -167,14 +167,57 @@ struct RotorClass {
     static constexpr bool MIXED = NRC == 0;
 };
 
+// sin and cos of an angle in radians.  For |x| < 4096 (every command angle in
+// practice): Cody-Waite reduction by pi/2 with pi/2 split into three FP32
+// parts (fl(pi/2), then fl of each remainder), applied by fused multiply-adds
+// (for |k| <= 2^12 the reduced argument carries an absolute error of a few
+// 1e-8 at most), then the Taylor polynomials of sin (to r^9) and cos (to
+// r^10) on [-pi/4, pi/4], whose truncation error is below 2e-9, and the
+// quadrant of k.  Larger or non-finite arguments take sincosf, in a branch of
+// their own lanes: a lane's result never depends on the other lanes.  This
+// replaces two full sincosf per vehicle and launch, whose large-argument
+// reduction (64-bit integer multiplies) is evaluated for every lane.
+AG_DEV void sincos_rad(float x, float& s, float& c) {
+    constexpr float kPio2a = 0x1.921fb6p+0f, kPio2b = -0x1.777a5cp-25f, kPio2c = -0x1.ee59dap-50f;
+    constexpr float k2Opi = 0x1.45f306p-1f;
+    const float k = __builtin_rintf(x * k2Opi);
+    float r = __builtin_fmaf(-k, kPio2a, x);
+    r = __builtin_fmaf(-k, kPio2b, r);
+    r = __builtin_fmaf(-k, kPio2c, r);
+    const float r2 = r * r;
+    // 1/9!, 1/7!, 1/5!, 1/3! and 1/10!, ..., 1/2! rounded to FP32
+    float ps = __builtin_fmaf(0x1.71de3ap-19f, r2, -0x1.a01a02p-13f);
+    ps = __builtin_fmaf(ps, r2, 0x1.111112p-7f);
+    ps = __builtin_fmaf(ps, r2, -0x1.555556p-3f);
+    ps = ps * r2;
+    float pc = __builtin_fmaf(-0x1.27e4fcp-22f, r2, 0x1.a01a02p-16f);
+    pc = __builtin_fmaf(pc, r2, -0x1.6c16c2p-10f);
+    pc = __builtin_fmaf(pc, r2, 0x1.555556p-5f);
+    pc = __builtin_fmaf(pc, r2, -0.5f);
+    // (sin of a signed zero keeps its sign)
+    const float sr = x == 0.0f ? x : __builtin_fmaf(r, ps, r);
+    const float cr = __builtin_fmaf(pc, r2, 1.0f);
+    // quadrant q = k mod 4: (sin, cos) = (s_r, c_r), (c_r, -s_r), (-s_r, -c_r), (-c_r, s_r)
+    const int q = (int)k;
+    const bool odd = (q & 1) != 0;
+    const uint32_t sneg = (uint32_t)(q & 2) << 30, cneg = (uint32_t)((q + 1) & 2) << 30;
+    s = __uint_as_float(__float_as_uint(odd ? cr : sr) ^ sneg);
+    c = __uint_as_float(__float_as_uint(odd ? sr : cr) ^ cneg);
+    if (!(__builtin_fabsf(x) < 4096.0f)) sincosf(x, &s, &c);
+}
+
 AG_DEV void derive_cmd(Cmd& C, int mode, float t0, float t1, float t2, float t3) {
     C.mode = mode;
     C.t0 = t0; C.t1 = t1; C.t2 = t2; C.t3 = t3;
     // position mode: angle a = psi_d; attitude mode: a = phi_d, b = theta_d.
     const float a = (mode == 0) ? t3 : ((mode == 2) ? t0 : 0.0f);
     const float b = (mode == 2) ? t1 : 0.0f;
-    sincosf(a, &C.sa, &C.ca);
-    sincosf(b, &C.sb, &C.cb);
+    // (sincos_rad gives exactly (x, 1) at x = +-0, so wavefronts whose angles
+    // are all zero skip it with the same results)
+    C.sa = a; C.ca = 1.0f;
+    C.sb = b; C.cb = 1.0f;
+    if (__any(a != 0.0f)) sincos_rad(a, C.sa, C.ca);
+    if (__any(b != 0.0f)) sincos_rad(b, C.sb, C.cb);
 }
 
 // Position-mode command to goal (gx, gy, gz) with psi_d = 0: the same fields
@@ -190,7 +233,7 @@ AG_DEV void derive_traj(Cmd& C, const float* __restrict__ tr, int64_t ld, int64_
     C.xd0 = tr[i]; C.xd1 = tr[ld + i]; C.xd2 = tr[2 * ld + i];
     C.vd0 = tr[3 * ld + i]; C.vd1 = tr[4 * ld + i]; C.vd2 = tr[5 * ld + i];
     C.ad0 = tr[6 * ld + i]; C.ad1 = tr[7 * ld + i]; C.ad2 = tr[8 * ld + i];
-    sincosf(tr[9 * ld + i], &C.spd, &C.cpd);
+    sincos_rad(tr[9 * ld + i], C.spd, C.cpd);
     C.wd0 = tr[10 * ld + i]; C.wd1 = tr[11 * ld + i]; C.wd2 = tr[12 * ld + i];
     C.dwd0 = tr[13 * ld + i]; C.dwd1 = tr[14 * ld + i]; C.dwd2 = tr[15 * ld + i];
 }
