@@ -55,11 +55,11 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # SQ_WAVES / steps) for 20-step and 1,024-step launches.  Valid only while
 # the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "c412a8e1976df2bf",
-    "per_step_bytes": 126992589.0,
-    "fused_bytes": 132265882.0,
-    "fused_valu_per_vstep": {20: 161.5, 1024: 139.9},
-    "per_step_4M_bytes": 508686336.0,
+    "src": "be6770bc6fc80baf",
+    "per_step_bytes": 127004467.0,
+    "fused_bytes": 132460646.0,
+    "fused_valu_per_vstep": {20: 151.2, 1024: 140.0},
+    "per_step_4M_bytes": 508690432.0,
     "profile": "profiles/fused_step_1M_quads.md",
 }
 
@@ -76,15 +76,15 @@ def valu_per_vstep(steps_per_launch):
 # (200 steps per call): VALU instructions per vehicle-step (forward; adjoint
 # counting its reverse and recompute wavefronts) and bytes per call.
 ROLLOUT_COUNTERS = {
-    "fwd_valu_per_vstep": 157.3,
-    "adj_valu_per_vstep": 641.4,
-    "fwd_bytes": 43072184.0,
-    "adj_bytes": 1405685760.0,
+    "fwd_valu_per_vstep": 157.0,
+    "adj_valu_per_vstep": 640.7,
+    "fwd_bytes": 43081503.0,
+    "adj_bytes": 1405732864.0,
     "profile": "profiles/rollout_65536_quads.md",
 }
 ROLLOUT_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_rollout.hip",
                    "paper_2305_16510_amd/csrc/ag_internal.h")
-ROLLOUT_SRC = "12c60b2535ea71d1"
+ROLLOUT_SRC = "c7acc834fab6a190"
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
                 "paper_2305_16510_amd/csrc/ag_internal.h")
 PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090
