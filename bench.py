@@ -149,11 +149,14 @@ def timed_with_events(stream, fn, sync):
     """(wall seconds, event seconds) of fn()'s launches: the wall clock runs
     from a device synchronisation before the launches to one after them, and
     events recorded on `stream` around the launches give the device time
-    (read after the closing synchronisation)."""
+    (read after the closing synchronisation).  The first event is recorded
+    just before the wall clock starts, so that its host-side cost is not
+    part of the timed work (the device interval then also holds the host's
+    launch of the work, a conservative kernel time)."""
     e0, e1 = _events()
     sync()
-    t0 = time.perf_counter()
     e0.record(stream)
+    t0 = time.perf_counter()
     fn()
     e1.record(stream)
     sync()
