@@ -55,11 +55,11 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # SQ_WAVES / steps) for 20-step and 1,024-step launches.  Valid only while
 # the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "be6770bc6fc80baf",
-    "per_step_bytes": 127004467.0,
-    "fused_bytes": 132460646.0,
+    "src": "aeca6f057e17a430",
+    "per_step_bytes": 126988902.0,
+    "fused_bytes": 132000627.0,
     "fused_valu_per_vstep": {20: 151.2, 1024: 140.0},
-    "per_step_4M_bytes": 508690432.0,
+    "per_step_4M_bytes": 508672000.0,
     "profile": "profiles/fused_step_1M_quads.md",
 }
 
@@ -78,13 +78,13 @@ def valu_per_vstep(steps_per_launch):
 ROLLOUT_COUNTERS = {
     "fwd_valu_per_vstep": 157.0,
     "adj_valu_per_vstep": 640.7,
-    "fwd_bytes": 43081503.0,
-    "adj_bytes": 1405732864.0,
+    "fwd_bytes": 43080233.0,
+    "adj_bytes": 1405851648.0,
     "profile": "profiles/rollout_65536_quads.md",
 }
 ROLLOUT_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_rollout.hip",
                    "paper_2305_16510_amd/csrc/ag_internal.h")
-ROLLOUT_SRC = "c7acc834fab6a190"
+ROLLOUT_SRC = "eb0da4d6695e7dec"
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
                 "paper_2305_16510_amd/csrc/ag_internal.h")
 PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090

@@ -197,8 +197,11 @@ AG_DEV void sincos_rad(float x, float& s, float& c) {
     // (sin of a signed zero keeps its sign)
     const float sr = x == 0.0f ? x : __builtin_fmaf(r, ps, r);
     const float cr = __builtin_fmaf(pc, r2, 1.0f);
-    // quadrant q = k mod 4: (sin, cos) = (s_r, c_r), (c_r, -s_r), (-s_r, -c_r), (-c_r, s_r)
-    const int q = (int)k;
+    // quadrant q = k mod 4: (sin, cos) = (s_r, c_r), (c_r, -s_r), (-s_r, -c_r), (-c_r, s_r);
+    // k is an integer of magnitude below 2^22 on this path, so k + 1.5 * 2^23
+    // holds k mod 2^23 in its low mantissa bits (no float-to-int conversion,
+    // which a non-finite k of the other path would make undefined)
+    const int q = __float_as_int(k + 0x1.8p23f) & 3;
     const bool odd = (q & 1) != 0;
     const uint32_t sneg = (uint32_t)(q & 2) << 30, cneg = (uint32_t)((q + 1) & 2) << 30;
     s = __uint_as_float(__float_as_uint(odd ? cr : sr) ^ sneg);

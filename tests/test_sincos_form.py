@@ -38,7 +38,7 @@ def sincos_form(x):
         pc = fma(pc, r2, np.full_like(x, c))
     sr = np.where(x == 0, x, fma(r, ps, r))
     cr = fma(pc, r2, np.ones_like(x))
-    q = k.astype(np.int64) & 3
+    q = (k + F32(1.5 * 2.0 ** 23)).view(np.int32) & 3     # k mod 4 from the float's low bits
     odd = (q & 1) == 1
     s = np.where(odd, cr, sr)
     c = np.where(odd, sr, cr)
