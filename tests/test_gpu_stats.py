@@ -77,6 +77,38 @@ def test_nonfinite_vehicles_are_flagged_not_fatal():
     assert np.isfinite(ok[:, ~nonfinite]).all()
 
 
+def test_nonfinite_command_angles():
+    """A NaN or infinite yaw command gives its vehicle a non-finite commanded
+    wrench (the sine and cosine of such an angle are NaN), which the
+    median-of-three clamp maps to rotor bounds: the applied wrench and the
+    state stay finite and no vehicle is flagged.  Huge finite angles (the
+    library sine/cosine branch of the kernels) and every other vehicle are
+    unaffected; per-step and fused launches alike."""
+    need_gpu()
+    for ex in (dict(kind=0, block=64, use_graph=0), dict(kind=1, block=128, vpl=1, k=5, grid=0, use_graph=1)):
+        wl = workloads.c1_parity(n=1000, seed=54)
+        wl.target[3, 20] = np.nan
+        wl.target[3, 30] = np.inf
+        wl.target[3, 40] = 5000.0
+        wl.target[3, 41] = -1e30
+        sim = make_sim(wl, collect_stats=True, outputs=True)
+        sim.set_exec(**ex)
+        sim.step(5)
+        st = sim.stats()
+        flags = sim.flags.cpu().numpy()
+        w = sim.wrench.cpu().numpy()
+        s = sim.state.cpu().numpy()
+        sim.close()
+        bad = np.zeros(1000, bool)
+        bad[[20, 30]] = True
+        assert st["n_nonfinite"] == 0 and st["n_finite"] == 1000
+        assert not (flags & 1).any()
+        assert np.isfinite(s).all()
+        assert not np.isfinite(w[0:4, bad]).all(axis=0).any()      # commanded wrench
+        assert np.isfinite(w[4:8]).all()                            # applied wrench
+        assert np.isfinite(w[0:4, ~bad]).all()
+
+
 def test_set_targets_copies_and_counts_invalid_modes():
     need_gpu()
     wl = workloads.c1_parity(n=3000, seed=53)
