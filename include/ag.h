@@ -131,7 +131,16 @@ typedef struct {
  * null.  Every policy gives bitwise identical states.  With automatic resets
  * a fused launch first finds, lists and redraws the resets of its k steps
  * (k <= 64 then) in dense kernels, holding up to one event per vehicle in
- * the workspace; events beyond that are redrawn in the step loop. */
+ * the workspace; events beyond that are redrawn in the step loop.
+ * kind 2: the fused kernel in work-queue form (block 64, vpl 1; a single
+ * vehicle group and no observers, trajectories, per-vehicle parameters or
+ * automatic resets, else AG_E_INVALID): a grid of grid wavefronts (0: as
+ * many as the chip holds at once; rounded down to a multiple of 64, at
+ * least 64) takes tiles of 64 vehicles on demand from 64 queues in the
+ * workspace and copies the next tile's rows into LDS while it steps the
+ * current one.
+ * Launches of one handle share the queues, so they must not overlap (they
+ * are ordered on the handle's stream). */
 typedef struct {
     int32_t kind, block, vpl, k, grid, use_graph;
 } ag_exec;

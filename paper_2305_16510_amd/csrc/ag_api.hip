@@ -66,7 +66,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct WsLayout {
     size_t gtab, goff, d_step, acc, slots, block_counts, mask, scratch, total;
     size_t ev_bits, ev_off, ev_bc, ev_total, ev_list, ev_data;
-    size_t perm;
+    size_t perm, queue;
     long long nslots, nblocks, ev_cap;
 };
 
@@ -83,6 +83,7 @@ WsLayout ws_layout(const ag_config* c) {
     L.block_counts = off; off = align_up(off + (size_t)L.nblocks * sizeof(int32_t));
     L.mask = off; off = align_up(off + (size_t)c->n);
     L.perm = off; off = align_up(off + (size_t)c->n * sizeof(int32_t));
+    L.queue = off; off = align_up(off + (size_t)kQueueWords * sizeof(unsigned));
     L.scratch = off;
     if (c->autotune_scratch) off = align_up(off + (size_t)(AG_STATE_DIM + AG_TARGET_DIM) * c->ld * sizeof(float));
     // reset events of fused launches (automatic resets): room for n events per
@@ -132,6 +133,8 @@ struct ag_sim {
     StatAcc* acc;
     StatSlot* slots;
     int32_t* perm;          // mode order of fused launches
+    unsigned* queue;        // tile queues of the work-queue kernel (zero between launches)
+    int q_occ;              // its wavefronts per CU (0: not yet queried, -1: query failed)
     bool order_valid;       // perm was computed since the last change of commands
     int32_t* block_counts;
     uint8_t* mask_buf;
@@ -374,6 +377,7 @@ StepArgs base_args(ag_handle h) {
         a.hi[k] = h->cfg.reset_hi[k];
     }
     a.ev = h->ev;
+    a.queue = h->queue;
     return a;
 }
 
@@ -385,7 +389,7 @@ bool uses_events(ag_handle h, const ag_exec& e) { return h->reset_on && e.kind =
 // have the mode-specialised step loops).
 bool order_policy(ag_handle h, const ag_exec& e) {
     const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
-    return e.kind == 1 && e.vpl == 1 && h->cfg.traj == nullptr && !obs && !h->reset_on;
+    return (e.kind == 1 || e.kind == 2) && e.vpl == 1 && h->cfg.traj == nullptr && !obs && !h->reset_on;
 }
 
 // Whether the fused launches of an ag_step of n_steps steps run in mode order.
@@ -436,8 +440,41 @@ struct LaunchShape {
     int span;
 };
 
+// Launch shape of the work-queue kernel (exec kind 2).
+std::string queue_shape(ag_handle h, const ag_exec& e, LaunchShape& s) {
+    if (e.block != 64) return "exec kind 2 needs block 64";
+    if (e.vpl != 1) return "exec kind 2 needs vpl 1";
+    if (e.k < 1) return "exec.k must be >= 1";
+    if (e.grid < 0) return "exec.grid must be >= 0";
+    const bool obs = h->cfg.wrench_out || h->cfg.rotor_out || h->cfg.flags_out || h->cfg.collect_stats;
+    if (h->cfg.n_groups != 1 || h->vp || obs || h->cfg.traj || h->reset_on)
+        return "exec kind 2 needs one vehicle group and no observers, trajectories, per-vehicle parameters "
+               "or automatic resets";
+    s.fn = step_queue_kernel(h->nr_class);
+    s.fn_fb = nullptr;
+    s.shmem = step_queue_lds_bytes();
+    if (!s.fn) return "no kernel for this combination of policy and configuration";
+    if (h->q_occ == 0) {
+        int occ = 0;
+        h->q_occ = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, s.fn, 64, s.shmem) == hipSuccess && occ > 0
+                       ? occ : -1;
+    }
+    if (h->q_occ < 0 && e.grid == 0) return "exec kind 2: occupancy query failed (give exec.grid)";
+    // as many wavefronts as run at once, a multiple of the queue count (every
+    // queue served by as many wavefronts), and no more than the tiles need
+    const long long nq = 8LL * kQueueSub;
+    const long long ntiles = (h->cfg.n + 63) / 64;
+    long long grid = e.grid > 0 ? e.grid : (long long)h->num_cus * h->q_occ;
+    grid = std::min(grid / nq * nq, (ntiles + nq - 1) / nq * nq);
+    s.grid = dim3((unsigned)std::max(grid, nq));
+    s.block = dim3(64);
+    s.span = 1;
+    return "";
+}
+
 std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
-    if (e.kind != 0 && e.kind != 1) return "exec.kind must be 0 (per-step) or 1 (fused)";
+    if (e.kind == 2) return queue_shape(h, e, s);
+    if (e.kind != 0 && e.kind != 1) return "exec.kind must be 0 (per-step), 1 (fused) or 2 (fused, work queue)";
     if (e.block < 64 || e.block > 512 || e.block % 64) return "exec.block must be a multiple of 64 in [64, 512]";
     const bool one = e.kind == 0;
     const int vpl = one ? 1 : e.vpl;
@@ -637,6 +674,8 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
     h->acc = reinterpret_cast<StatAcc*>(h->ws + L.acc);
     h->slots = reinterpret_cast<StatSlot*>(h->ws + L.slots);
     h->perm = reinterpret_cast<int32_t*>(h->ws + L.perm);
+    h->queue = reinterpret_cast<unsigned*>(h->ws + L.queue);
+    h->q_occ = 0;
     h->block_counts = reinterpret_cast<int32_t*>(h->ws + L.block_counts);
     h->mask_buf = reinterpret_cast<uint8_t*>(h->ws + L.mask);
     h->scratch = cfg->autotune_scratch ? reinterpret_cast<float*>(h->ws + L.scratch) : nullptr;
@@ -693,6 +732,8 @@ ag_status ag_create(const ag_config* cfg, void* workspace, size_t workspace_byte
         e = hipMemcpyAsync(h->goff, h->goff_host.data(), h->goff_host.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h->acc, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream);
+    static const unsigned qzero[kQueueWords] = {};
+    if (e == hipSuccess) e = hipMemcpyAsync(h->queue, qzero, sizeof(qzero), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
         CounterArgs c{h->d_step, 0};
         void* p1[] = {&c};
@@ -971,6 +1012,9 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     ag_exec best = h->exec;
     float best_ms = 1e30f;
     const long long saved_t = h->t;
+    // the candidates: fused launches of every block, vpl and k, each on one
+    // block per tile and on a persistent grid, and the work-queue form
+    std::vector<ag_exec> cands;
     for (int b : blocks)
         for (int v : vpls)
             for (int k : ks) {
@@ -989,33 +1033,41 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
                         if (gp >= (long long)s.grid.x) continue;
                         cand.grid = (int)gp;
                     }
-                    float ms_min = 1e30f;
-                    for (int rep = 0; rep < reps; ++rep) {
-                        AG_HIP(h, hipMemcpy2DAsync(s_state, ld * sizeof(float), h->cfg.state, ld * sizeof(float),
-                                                   h->cfg.n * sizeof(float), AG_STATE_DIM, hipMemcpyDeviceToDevice,
-                                                   h->stream));
-                        AG_HIP(h, hipMemcpy2DAsync(s_target, ld * sizeof(float), h->cfg.target,
-                                                   ld * sizeof(float), h->cfg.n * sizeof(float), AG_TARGET_DIM,
-                                                   hipMemcpyDeviceToDevice, h->stream));
-                        AG_HIP(h, hipEventRecord(e0, h->stream));
-                        ag_status st = run_direct(h, cand, probe_steps, a, false);
-                        if (st != AG_OK) {
-                            (void)hipEventDestroy(e0);
-                            (void)hipEventDestroy(e1);
-                            return st;
-                        }
-                        AG_HIP(h, hipEventRecord(e1, h->stream));
-                        AG_HIP(h, hipEventSynchronize(e1));
-                        float ms = 0.0f;
-                        AG_HIP(h, hipEventElapsedTime(&ms, e0, e1));
-                        if (rep > 0) ms_min = std::min(ms_min, ms);
-                    }
-                    if (ms_min < best_ms) {
-                        best_ms = ms_min;
-                        best = cand;
-                    }
+                    cands.push_back(cand);
                 }
             }
+    for (int k : ks) {
+        if (k > probe_steps && k != 4) continue;
+        ag_exec cand{2, 64, 1, k, 0, h->exec.use_graph};
+        LaunchShape s;
+        if (shape_for(h, cand, s).empty()) cands.push_back(cand);
+    }
+    for (const ag_exec& cand : cands) {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < reps; ++rep) {
+            AG_HIP(h, hipMemcpy2DAsync(s_state, ld * sizeof(float), h->cfg.state, ld * sizeof(float),
+                                       h->cfg.n * sizeof(float), AG_STATE_DIM, hipMemcpyDeviceToDevice, h->stream));
+            AG_HIP(h, hipMemcpy2DAsync(s_target, ld * sizeof(float), h->cfg.target, ld * sizeof(float),
+                                       h->cfg.n * sizeof(float), AG_TARGET_DIM, hipMemcpyDeviceToDevice,
+                                       h->stream));
+            AG_HIP(h, hipEventRecord(e0, h->stream));
+            ag_status st = run_direct(h, cand, probe_steps, a, false);
+            if (st != AG_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return st;
+            }
+            AG_HIP(h, hipEventRecord(e1, h->stream));
+            AG_HIP(h, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            AG_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) ms_min = std::min(ms_min, ms);
+        }
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = cand;
+        }
+    }
     h->t = saved_t;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -42,6 +42,12 @@ struct EvBufs {
     long long cap;
 };
 
+// Work-queue kernel: kQueueSub queues per XCD, each with a ticket counter and
+// a done count in a line of kQueueLine words of its own.
+constexpr int kQueueSub = 8;
+constexpr int kQueueLine = 64;
+constexpr int kQueueWords = 8 * kQueueSub * kQueueLine;
+
 struct StepArgs {
     float* state;              // [13][ld] (read and written in place)
     const int8_t* mode;        // [ld]
@@ -70,6 +76,7 @@ struct StepArgs {
     float lo[3], hi[3];
     EvBufs ev;                 // reset events (RESET kernels)
     const int32_t* perm;       // [n] vehicle of each lane position (fused kernels), or null: identity
+    unsigned* queue;           // [kQueueWords] tile queues of the work-queue kernel (zero between launches)
 };
 
 struct ResetArgs {
@@ -120,6 +127,11 @@ constexpr int kMaxSpanLds = 160;   // groups per tile that fit the LDS budget
 // A fused launch with resets runs the rst = 2 and rst = 1 kernels in turn;
 // each leaves at once unless the launch's event count selects it.
 const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, bool obs, bool trk);
+// The work-queue form of the fused kernel (exec kind 2: single group, no
+// observers, resets, trajectories or per-vehicle parameters, one vehicle per
+// lane, blocks of 64) and its dynamic LDS.
+const void* step_queue_kernel(int nr_class);
+size_t step_queue_lds_bytes();
 const void* fold_kernel();
 const void* advance_kernel();
 const void* set_step_kernel();

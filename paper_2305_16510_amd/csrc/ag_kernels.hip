@@ -415,6 +415,161 @@ void k_step(StepArgs a) {
     step_tiles<NR, VP, RST, VPL, ONE, OBS, TRK, false>(a, lds, loff, sh);
 }
 
+// ---- fused steps from work queues, the next tile copied ahead --------------
+// Persistent form of the fused kernel for single-group fleets without
+// observers, resets, trajectories or per-vehicle parameters (one vehicle per
+// lane, blocks of one wavefront).  The grid holds as many wavefronts as the
+// chip runs at once, a multiple of the queue count.  The tiles (64 lane
+// positions each) are split into kQueueSub * 8 contiguous ranges, one per
+// queue, and block b serves queue (b mod 8, (b / 8) mod kQueueSub): blocks
+// are dealt to the XCDs round robin, so each XCD serves one contiguous eighth
+// of the tiles and the mode runs of a segment meet in one L2.  Wavefronts
+// sharing a SIMD run at very different speeds (the SIMD issues from its
+// oldest wavefront first), so after its first tile a wavefront takes tiles on
+// demand: it asks its queue for the next one a few steps before the current
+// one ends, late enough to hold on to little work the others could take.
+// The next tile's rows (state and command, 17 floats per lane) are then
+// copied into LDS by direct global-to-LDS loads, and its mode byte into a
+// register, while the last steps of the current tile run; the waits for the
+// ticket and the vehicle indices stall only this wavefront (the SIMD runs
+// the others).  Each queue's two counters have a 256-byte line of their own
+// (the atomics on one line are served one at a time); the last wavefront of
+// a queue to finish clears them for the next launch.
+constexpr int kQueueRows = 17;                  // floats per lane copied ahead
+constexpr int kLead = 3;                        // steps left in a tile when the next is asked for
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVm0 = 0x0F70;                // every vector memory access done
+constexpr int kWaitLgkm0 = 0xC07F;              // every LDS access done
+
+template <int NR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_step_q(StepArgs a) {
+    extern __shared__ float4 lds4[];
+    float* const lds = reinterpret_cast<float*>(lds4);   // the group entry
+    float* const buf = lds + GSTRIDE;                     // [kQueueRows][64]
+    const int lane = (int)threadIdx.x;
+    const long long n = a.n, ld = a.ld;
+    const int K = a.k;
+    const long long ntiles = (n + 63) >> 6;
+    constexpr int NQ = 8 * kQueueSub;
+    const int qi = (int)(blockIdx.x & 7) * kQueueSub + (int)((blockIdx.x >> 3) % kQueueSub);
+    const long long per = ntiles / NQ, rem = ntiles % NQ;
+    const long long r0 = qi * per + (qi < rem ? qi : rem);
+    const long long r1 = r0 + per + (qi < rem ? 1 : 0);
+    unsigned* const q = a.queue + qi * kQueueLine;       // [0] tickets handed out, [1] wavefronts done
+    const unsigned waves = gridDim.x / NQ;               // wavefronts serving this queue
+
+    // a ticket of this queue (lane 0; the offset is an opaque zero: with a
+    // visibly uniform address the compiler would combine the wavefront's
+    // atomics and read the result back at once, waiting for it there)
+    auto ticket = [&]() -> unsigned {
+        unsigned k = 0;
+        if (lane == 0) {
+            int zero;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+            k = atomicAdd(q + zero, 1u);
+        }
+        return k;
+    };
+    // lane position of tile t -> vehicle (mode order, or identity); positions
+    // past n take vehicle n - 1 and are not stored
+    auto vehicle = [&](long long t) -> int {
+        const long long p = t * 64 + lane;
+        const int pl = (int)(p < n ? p : n - 1);
+        return a.perm ? a.perm[pl] : pl;
+    };
+    // copy vehicle i's rows into this lane's column of the buffer
+    auto fetch = [&](int i) {
+#pragma unroll
+        for (int r = 0; r < 13; ++r) __builtin_amdgcn_global_load_lds(a.state + r * ld + i, buf + r * 64, 4, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) __builtin_amdgcn_global_load_lds(a.target + r * ld + i, buf + (13 + r) * 64, 4, 0, 0);
+    };
+
+    // the first tile is fixed: the wavefronts of a queue take its first tiles
+    // in block order, and its tickets count the tiles after those.  Its
+    // vehicles are asked for first, then the group entry (single group)
+    long long t_cur = r0 + (long long)(blockIdx.x / NQ);
+    int i_cur = t_cur < r1 ? vehicle(t_cur) : 0;
+    for (int e = lane; e < GSTRIDE; e += 64) lds[e] = a.gtab[e];
+    __syncthreads();
+    const float* gt = lds;
+    Params P;
+    load_params<false>(P, gt, nullptr, ld, 0);
+    // a SIMD issues from its oldest wavefront first, which would leave a
+    // young one on its first tile until the end: a wavefront's priority
+    // drops with each tile it completes, down to the lowest after three
+    __builtin_amdgcn_s_setprio(3);
+    int n_done = 0;
+    if (t_cur < r1) {
+        fetch(i_cur);
+        int md = a.mode[i_cur];
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        // the next tile is asked for kLead steps before the current one ends
+        // (at once for shorter launches): late enough that a wavefront holds
+        // on to little work the others could take, early enough that its
+        // rows arrive before they are needed
+        const int s_ask = K > kLead ? K - kLead : 0;
+        for (;;) {
+            // the current tile's rows, from LDS
+            float s[13], tg[4];
+#pragma unroll
+            for (int r = 0; r < 13; ++r) s[r] = buf[r * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tg[r] = buf[(13 + r) * 64 + lane];
+            const bool act = t_cur * 64 + lane < n;
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            long long t_nxt = r1;
+            int i_nxt = 0, md_nxt = 0;
+            Cmd C;
+            derive_cmd(C, md, tg[0], tg[1], tg[2], tg[3]);
+            auto run = [&](auto ms) {
+                constexpr int MS = decltype(ms)::value;
+                for (int st = 0; st < s_ask; ++st) step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+                const unsigned k = ticket();
+                __builtin_amdgcn_s_waitcnt(kWaitVm0);
+                t_nxt = r0 + waves + (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)k);
+                if (t_nxt < r1) {
+                    i_nxt = vehicle(t_nxt);
+                    fetch(i_nxt);
+                    md_nxt = a.mode[i_nxt];
+                }
+                for (int st = s_ask; st < K; ++st) step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+            };
+            const int m_first = __builtin_amdgcn_readfirstlane(md);
+            const int wm = __all(md == m_first) ? m_first : -1;
+            switch (wm) {
+            case 0: run(std::integral_constant<int, 0>{}); break;
+            case 1: run(std::integral_constant<int, 1>{}); break;
+            case 2: run(std::integral_constant<int, 2>{}); break;
+            default: run(std::integral_constant<int, -1>{}); break;
+            }
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            if (act) {
+#pragma unroll
+                for (int r = 0; r < 13; ++r) a.state[r * ld + i_cur] = s[r];
+            }
+            if (t_nxt >= r1) break;
+            ++n_done;
+            if (n_done == 1) __builtin_amdgcn_s_setprio(2);
+            else if (n_done == 2) __builtin_amdgcn_s_setprio(1);
+            else if (n_done == 3) __builtin_amdgcn_s_setprio(0);
+            t_cur = t_nxt;
+            i_cur = i_nxt;
+            md = md_nxt;
+        }
+    }
+    // every ticket of this wavefront has been served (the waits above); the
+    // last wavefront of the queue clears its counters for the next launch
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    if (lane == 0) {
+        const unsigned d = atomicAdd(q + 1, 1u);
+        if (d == waves - 1) {
+            atomicExch(q, 0u);
+            atomicExch(q + 1, 0u);
+        }
+    }
+}
+
 // ---- statistics fold: slots -> cumulative accumulator (one block) ---------
 __global__ __launch_bounds__(256) void k_fold(FoldArgs a) {
     __shared__ long long ri[256][5];
@@ -917,6 +1072,17 @@ const void* step_kernel(int nr_class, bool vp, int rst, int vpl, bool one_step, 
         default: return pick_nr<0, false>(vp, rst, vpl, one_step, obs);
     }
 }
+
+const void* step_queue_kernel(int nr_class) {
+    switch (nr_class) {
+        case 4: return reinterpret_cast<const void*>(&k_step_q<4>);
+        case 6: return reinterpret_cast<const void*>(&k_step_q<6>);
+        case 8: return reinterpret_cast<const void*>(&k_step_q<8>);
+        default: return nullptr;   // one group: its rotor count is 4, 6 or 8
+    }
+}
+
+size_t step_queue_lds_bytes() { return (size_t)(GSTRIDE + kQueueRows * 64) * sizeof(float); }
 
 const void* fold_kernel() { return reinterpret_cast<const void*>(&k_fold); }
 const void* advance_kernel() { return reinterpret_cast<const void*>(&k_advance); }

@@ -26,7 +26,7 @@ def expect(status, fn):
     return str(e.value)
 
 
-@pytest.mark.parametrize("bad", [dict(kind=2), dict(block=100), dict(block=1024), dict(vpl=3),
+@pytest.mark.parametrize("bad", [dict(kind=3), dict(kind=2), dict(kind=2, block=64, vpl=2), dict(block=100), dict(block=1024), dict(vpl=3),
                                  dict(kind=1, k=0), dict(grid=-1)])
 def test_invalid_exec_policies(bad):
     need_gpu()
