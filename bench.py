@@ -50,26 +50,33 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE / WRITE_SIZE on the
 # 1,048,576-quad workload, scaled by what the same counters read for a plain
 # 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0): per-step kernel, and a
-# fused launch (one load and one store of the state per launch, whatever k);
-# VALU instructions per vehicle-step of the fused kernel (SQ_INSTS_VALU /
-# SQ_WAVES / steps) for 20-step and 1,024-step launches.  Valid only while
-# the step-kernel sources hash to ``src``.
+# fused launch of each fused form (exec kind 1: one block per tile; kind 2:
+# work queues) at 20 steps (one load and one store of the state per launch,
+# whatever k); VALU instructions per vehicle-step of each form (SQ_INSTS_VALU
+# x 64 lanes / vehicles / steps) for 20-step and 512-step launches.  Valid
+# only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "aeca6f057e17a430",
-    "per_step_bytes": 126988902.0,
-    "fused_bytes": 132000627.0,
-    "fused_valu_per_vstep": {20: 151.2, 1024: 140.0},
-    "per_step_4M_bytes": 508672000.0,
+    "src": "1606636980b5c059",
+    "per_step_bytes": 127001805.0,
+    "fused": {1: {"bytes": 131977216.0, "valu_per_vstep": {20: 151.2, 512: 140.0}},
+              2: {"bytes": 238952243.0, "valu_per_vstep": {20: 147.1, 512: 139.8}}},
+    "per_step_4M_bytes": 508684288.0,
     "profile": "profiles/fused_step_1M_quads.md",
 }
+FUSED_KERNELS = {1: "k_step fused (one block per tile)", 2: "k_step_q fused (work queues)"}
 
 
-def valu_per_vstep(steps_per_launch):
-    """Counted VALU instructions per vehicle-step for launches of this many
-    steps (the per-launch set-up spreads over fewer steps in short launches:
-    the 20-step figure below 64 steps, the 1,024-step figure from there)."""
-    v = COUNTERS["fused_valu_per_vstep"]
-    return v[20] if steps_per_launch < 64 else v[1024]
+def fused_counters(kind):
+    return COUNTERS["fused"].get(kind, {"bytes": None, "valu_per_vstep": {20: None, 512: None}})
+
+
+def valu_per_vstep(kind, steps_per_launch):
+    """Counted VALU instructions per vehicle-step of fused launches of this
+    form and this many steps (the per-launch set-up spreads over fewer steps
+    in short launches: the 20-step figure below 64 steps, the 512-step figure
+    from there)."""
+    v = fused_counters(kind)["valu_per_vstep"]
+    return v[20] if steps_per_launch < 64 else v[512]
 
 
 # The same for the rollout kernels of the 65,536-quad differentiation leg
@@ -84,7 +91,7 @@ ROLLOUT_COUNTERS = {
 }
 ROLLOUT_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_rollout.hip",
                    "paper_2305_16510_amd/csrc/ag_internal.h")
-ROLLOUT_SRC = "eb0da4d6695e7dec"
+ROLLOUT_SRC = "5553e34538b62d5b"
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
                 "paper_2305_16510_amd/csrc/ag_internal.h")
 PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090
@@ -408,7 +415,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-step", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--exec", type=str, default="", help="fixed fused policy 'block,vpl,k,grid' (skips tuning)")
+    ap.add_argument("--exec", type=str, default="",
+                    help="fixed fused policy '[kind,]block,vpl,k,grid' (kind 1 if omitted; skips tuning)")
     ap.add_argument("--per-step-block", type=int, default=0, help="fixed block of the per-step kernel (skips its sweep)")
     ap.add_argument("--cpu-sample", type=int, default=65_536)
     ap.add_argument("--cpu-steps", type=int, default=300)
@@ -445,8 +453,9 @@ def main():
     sim = Sim.from_workload(wl, autotune_scratch=True)
     sync = torch.cuda.synchronize
     if args.exec:
-        b, v, k, g = (int(x) for x in args.exec.split(","))
-        sim.set_exec(kind=1, block=b, vpl=v, k=k, grid=g, use_graph=1)
+        f = [int(x) for x in args.exec.split(",")]
+        kd, b, v, k, g = f if len(f) == 5 else [1] + f
+        sim.set_exec(kind=kd, block=b, vpl=v, k=k, grid=g, use_graph=1)
         tuned = sim.get_exec()
     else:
         # the policy for calls of K steps, from trials of K-step calls
@@ -485,11 +494,13 @@ def main():
     t_fix = min(event_time(sim.stream, lambda: sim.raw_step(fixed_steps)) for _ in range(3))
     fix_launches = math.ceil(fixed_steps / k_fixed)
     fix_tflops = FLOPS_PER_VSTEP * wl.n * fixed_steps / t_fix / 1e12
-    fix_valu = valu_per_vstep(min(fixed_steps, k_fixed))
-    roofline_fixed = {"valu_instr_per_vehicle_step": fix_valu if counters_valid() else None,
+    fc_fixed = fused_counters(tuned_fixed["kind"])
+    fix_valu = valu_per_vstep(tuned_fixed["kind"], min(fixed_steps, k_fixed)) if counters_valid() else None
+    roofline_fixed = {"kernel": FUSED_KERNELS.get(tuned_fixed["kind"]),
+                      "valu_instr_per_vehicle_step": fix_valu,
                       "valu_issue_frac_of_peak": (fix_valu * wl.n * fixed_steps / t_fix) / (FP32_PEAK_TFLOPS * 1e12 / 2)
-                      if counters_valid() else None,
-                      "traffic": COUNTERS["fused_bytes"] if counters_valid() else None,
+                      if fix_valu else None,
+                      "traffic": fc_fixed["bytes"] if counters_valid() else None,
                       "steps": fixed_steps, "exec": tuned_fixed, "launches": fix_launches,
                       "steps_per_launch": min(fixed_steps, k_fixed),
                       "kernel_avg_us": t_fix / fix_launches * 1e6, "us_per_step": t_fix / fixed_steps * 1e6,
@@ -553,8 +564,8 @@ def main():
     valid = counters_valid()
     # VALU utilisation: lane-instructions issued per second against the chip's
     # peak issue rate (157.3 TFLOP/s = 78.6e12 single-lane FMAs per second)
-    valu_vstep = valu_per_vstep(min(K, k))
-    valu_util = (valu_vstep * wl.n * K / t_evt["fused"]) / (FP32_PEAK_TFLOPS * 1e12 / 2) if valid else None
+    valu_vstep = valu_per_vstep(tuned["kind"], min(K, k)) if valid else None
+    valu_util = (valu_vstep * wl.n * K / t_evt["fused"]) / (FP32_PEAK_TFLOPS * 1e12 / 2) if valu_vstep else None
     out = {
         "metric": "vehicle-steps/s at 1M quads (fused vs per-step), %HBM/VALU peak; adjoint s/step",
         "value": value,
@@ -575,14 +586,14 @@ def main():
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": tflops / FP32_PEAK_TFLOPS,
                      # one load and one store of the state per launch, whatever k
-                     "traffic": COUNTERS["fused_bytes"] if valid else None,
-                     "kernel": "k_step fused", "kernel_avg_us": kern_fused * 1e6,
+                     "traffic": fused_counters(tuned["kind"])["bytes"] if valid else None,
+                     "kernel": FUSED_KERNELS.get(tuned["kind"]), "kernel_avg_us": kern_fused * 1e6,
                      "launches": launches, "steps_per_launch": min(K, k),
                      "flops_per_vehicle_step": FLOPS_PER_VSTEP,
                      "counted": {"flops_per_vehicle_step": fl_count, "achieved": tflops_count,
                                  "frac": tflops_count / FP32_PEAK_TFLOPS,
                                  "what": "per-mode operation count of the fleet's modes (not the headline)"},
-                     "valu_instr_per_vehicle_step": valu_vstep if valid else None,
+                     "valu_instr_per_vehicle_step": valu_vstep,
                      "valu_issue_frac_of_peak": valu_util,
                      "counters": COUNTERS["profile"] if valid else "stale: kernel changed since counters"},
         "roofline_fixed_shape": roofline_fixed,

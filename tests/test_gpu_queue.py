@@ -51,6 +51,22 @@ def test_mixed_modes_in_mode_order(k, grid, graph):
     assert torch.equal(got, ref)
 
 
+@pytest.mark.parametrize("n,modes", [(600_011, None), (300_000, 0)])
+def test_queues_with_whole_segments(n, modes):
+    """Queues longer than a segment of the mode order (64 tiles), so that
+    wavefronts take tiles on demand long after their first; a ragged fleet
+    with every mode, and an all-position fleet (n = 300,000: 73 or 74 tiles
+    a queue)."""
+    need_gpu()
+    wl = mixed(n, 84)
+    if modes is not None:
+        wl.mode[:] = modes
+    assert (n + 63) // 64 // 64 >= 64                      # at least 64 tiles a queue
+    ref = run(wl, PLAIN, [40])
+    got = run(wl, dict(kind=2, block=64, vpl=1, k=13, grid=0, use_graph=1), [40])
+    assert torch.equal(got, ref)
+
+
 def test_short_calls_without_order():
     need_gpu()
     wl = mixed(30_001, 82)
