@@ -135,8 +135,8 @@ typedef struct {
  * kind 2: the fused kernel in work-queue form (block 64, vpl 1; a single
  * vehicle group and no observers, trajectories, per-vehicle parameters or
  * automatic resets, else AG_E_INVALID): a grid of grid wavefronts (0: as
- * many as the chip holds at once; rounded down to a multiple of 64, at
- * least 64) takes tiles of 64 vehicles on demand from 64 queues in the
+ * many as the chip holds at once; rounded down to a multiple of 32, at
+ * least 32) takes tiles of 64 vehicles on demand from 32 queues in the
  * workspace and copies the next tile's rows into LDS while it steps the
  * current one.
  * Launches of one handle share the queues, so they must not overlap (they

@@ -44,7 +44,7 @@ struct EvBufs {
 
 // Work-queue kernel: kQueueSub queues per XCD, each with a ticket counter and
 // a done count in a line of kQueueLine words of its own.
-constexpr int kQueueSub = 8;
+constexpr int kQueueSub = 4;
 constexpr int kQueueLine = 64;
 constexpr int kQueueWords = 8 * kQueueSub * kQueueLine;
 

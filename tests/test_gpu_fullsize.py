@@ -3,7 +3,8 @@ configuration the benchmark times (autotuned fused policy replayed from a HIP
 graph) against plain per-step launches and the FP64 oracle on sampled
 vehicles.
 
-* fused and per-step final states bitwise identical after 1,000 steps;
+* fused (autotuned, and each fused form in the shapes the benchmark tunes
+  to) and per-step final states bitwise identical after 1,000 steps;
 * one step from the GPU's FP32 state at step 999 reproduces the GPU's step
   1,000 within FP32 rounding of the oracle (relative 1e-5, unit floor), on
   4,096 sampled vehicles of every mode;
@@ -51,6 +52,29 @@ def full_c2():
 def test_fused_equals_per_step_at_full_size(full_c2):
     _, r = full_c2
     assert torch.equal(r["fused"], r["plain"])
+
+
+@pytest.mark.parametrize("policy", [dict(kind=2, block=64, vpl=1, k=20, grid=0, use_graph=1),
+                                    dict(kind=2, block=64, vpl=1, k=512, grid=0, use_graph=1),
+                                    dict(kind=1, block=256, vpl=1, k=20, grid=0, use_graph=1)])
+def test_each_fused_form_at_full_size(full_c2, policy):
+    """Both fused forms (work queues and one block per tile) in the shapes the
+    benchmark tunes to, 1,000 steps in 20-step calls and in one call,
+    against the per-step launches."""
+    wl, r = full_c2
+    from paper_2305_16510_amd.sim import Sim
+    sim = Sim.from_workload(wl)
+    sim.set_exec(**policy)
+    if policy["k"] == 20:
+        sim.prepare(20)
+        for _ in range(50):
+            sim.step(20)
+    else:
+        sim.step(1000)
+    sim.sync()
+    got = sim.state.clone()
+    sim.close()
+    assert torch.equal(got, r["plain"]), policy
 
 
 def test_sampled_one_step_parity_at_step_1000(full_c2):

@@ -55,13 +55,13 @@ def test_mixed_modes_in_mode_order(k, grid, graph):
 def test_queues_with_whole_segments(n, modes):
     """Queues longer than a segment of the mode order (64 tiles), so that
     wavefronts take tiles on demand long after their first; a ragged fleet
-    with every mode, and an all-position fleet (n = 300,000: 73 or 74 tiles
-    a queue)."""
+    with every mode, and an all-position fleet (n = 300,000: 146 or 147
+    tiles a queue)."""
     need_gpu()
     wl = mixed(n, 84)
     if modes is not None:
         wl.mode[:] = modes
-    assert (n + 63) // 64 // 64 >= 64                      # at least 64 tiles a queue
+    assert (n + 63) // 64 // 32 >= 64                      # at least 64 tiles a queue
     ref = run(wl, PLAIN, [40])
     got = run(wl, dict(kind=2, block=64, vpl=1, k=13, grid=0, use_graph=1), [40])
     assert torch.equal(got, ref)
@@ -87,7 +87,7 @@ def test_hexa_and_octo_layouts(nr):
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 300, 511, 513, 4097])
 def test_few_tiles_and_ragged_tails(n):
-    """Fewer tiles than the 64 queues (n <= 4032: some queues hand out
+    """Fewer tiles than the 32 queues (n <= 1984: some queues hand out
     nothing) and last tiles of 1 to 63 vehicles."""
     need_gpu()
     wl = mixed(n, 90 + n)
