@@ -482,39 +482,14 @@ def main():
     log(f"fused: {t_fused * 1e3:.3f} ms for {K} steps -> {value:.3e} vehicle-steps/s; "
         f"kernel avg {kern_fused * 1e6:.1f} us over {launches} launches")
 
-    # ---- the profiled launch shape: 1,024 steps under the same policy --------
-    # (outside the headline timing; with k = 512 these are two full launches,
-    # the shape of the committed counter profile)
-    fixed_steps = 1024
-    tuned_fixed = sim.get_exec() if args.exec else sim.autotune(fixed_steps)
-    k_fixed = tuned_fixed["k"]
-    sim.prepare(fixed_steps)
-    sim.raw_step(fixed_steps)
-    sync()
-    t_fix = min(event_time(sim.stream, lambda: sim.raw_step(fixed_steps)) for _ in range(3))
-    fix_launches = math.ceil(fixed_steps / k_fixed)
-    fix_tflops = FLOPS_PER_VSTEP * wl.n * fixed_steps / t_fix / 1e12
-    fc_fixed = fused_counters(tuned_fixed["kind"])
-    fix_valu = valu_per_vstep(tuned_fixed["kind"], min(fixed_steps, k_fixed)) if counters_valid() else None
-    roofline_fixed = {"kernel": FUSED_KERNELS.get(tuned_fixed["kind"]),
-                      "valu_instr_per_vehicle_step": fix_valu,
-                      "valu_issue_frac_of_peak": (fix_valu * wl.n * fixed_steps / t_fix) / (FP32_PEAK_TFLOPS * 1e12 / 2)
-                      if fix_valu else None,
-                      "traffic": fc_fixed["bytes"] if counters_valid() else None,
-                      "steps": fixed_steps, "exec": tuned_fixed, "launches": fix_launches,
-                      "steps_per_launch": min(fixed_steps, k_fixed),
-                      "kernel_avg_us": t_fix / fix_launches * 1e6, "us_per_step": t_fix / fixed_steps * 1e6,
-                      "value": wl.n * fixed_steps / t_fix, "achieved": fix_tflops, "unit": "TFLOP/s",
-                      "frac": fix_tflops / FP32_PEAK_TFLOPS,
-                      "counted_frac": flops_per_vstep(wl.mode) * wl.n * fixed_steps / t_fix / 1e12 / FP32_PEAK_TFLOPS}
-    log(f"fixed shape: {fixed_steps} steps in {fix_launches} launches, {t_fix / fixed_steps * 1e6:.2f} us/step, "
-        f"frac {roofline_fixed['frac']:.3f}")
-
     # ---- plain per-step launches ----------------------------------------------
     # K kernel launches without a graph, issued by the library's own launch
     # loop (ag_step(K) under the per-step policy); the same K steps as K host
     # calls of ag_step(1) are timed as well, where the host's per-call time
-    # can leave the GPU idle between launches.
+    # can leave the GPU idle between launches.  Timed right after the fused
+    # call, each after its own short search (block sweep, autotune), so that
+    # the GPU's clocks are in the same state for both (the 1,024-step leg's
+    # search below keeps the GPU busy for about a second and raises them).
     per_step = None
     if not args.no_per_step:
         sweep = {}
@@ -555,6 +530,38 @@ def main():
         }
         log(f"per-step: {t_plain * 1e3:.2f} ms -> {per_step['value']:.3e} vehicle-steps/s, "
             f"kernel {kern_plain * 1e6:.1f} us = {gbs:.0f} GB/s; as host calls {t_calls * 1e3:.2f} ms")
+
+    # ---- the profiled launch shape: 1,024 steps under the same policy --------
+    # (outside the headline timing; with k = 512 these are two full launches,
+    # the shape of the committed counter profile)
+    fixed_steps = 1024
+    if args.exec:
+        sim.set_exec(**tuned)
+        tuned_fixed = tuned
+    else:
+        tuned_fixed = sim.autotune(fixed_steps)
+    k_fixed = tuned_fixed["k"]
+    sim.prepare(fixed_steps)
+    sim.raw_step(fixed_steps)
+    sync()
+    t_fix = min(event_time(sim.stream, lambda: sim.raw_step(fixed_steps)) for _ in range(3))
+    fix_launches = math.ceil(fixed_steps / k_fixed)
+    fix_tflops = FLOPS_PER_VSTEP * wl.n * fixed_steps / t_fix / 1e12
+    fc_fixed = fused_counters(tuned_fixed["kind"])
+    fix_valu = valu_per_vstep(tuned_fixed["kind"], min(fixed_steps, k_fixed)) if counters_valid() else None
+    roofline_fixed = {"kernel": FUSED_KERNELS.get(tuned_fixed["kind"]),
+                      "valu_instr_per_vehicle_step": fix_valu,
+                      "valu_issue_frac_of_peak": (fix_valu * wl.n * fixed_steps / t_fix) / (FP32_PEAK_TFLOPS * 1e12 / 2)
+                      if fix_valu else None,
+                      "traffic": fc_fixed["bytes"] if counters_valid() else None,
+                      "steps": fixed_steps, "exec": tuned_fixed, "launches": fix_launches,
+                      "steps_per_launch": min(fixed_steps, k_fixed),
+                      "kernel_avg_us": t_fix / fix_launches * 1e6, "us_per_step": t_fix / fixed_steps * 1e6,
+                      "value": wl.n * fixed_steps / t_fix, "achieved": fix_tflops, "unit": "TFLOP/s",
+                      "frac": fix_tflops / FP32_PEAK_TFLOPS,
+                      "counted_frac": flops_per_vstep(wl.mode) * wl.n * fixed_steps / t_fix / 1e12 / FP32_PEAK_TFLOPS}
+    log(f"fixed shape: {fixed_steps} steps in {fix_launches} launches, {t_fix / fixed_steps * 1e6:.2f} us/step, "
+        f"frac {roofline_fixed['frac']:.3f}")
 
     # achieved = algorithmic flops of the timed launches / their event time
     # (the last launch of a K that k does not divide runs fewer steps)

@@ -1007,8 +1007,10 @@ ag_status ag_autotune(ag_handle h, int32_t probe_steps, ag_exec* chosen) {
     // launch per call)
     std::vector<int> ks = {4, 8, 16, 32, 64, 128, 256, 512, 1024};
     if (probe_steps <= 1024 && std::find(ks.begin(), ks.end(), probe_steps) == ks.end()) ks.push_back(probe_steps);
-    // short trials are noisier: more repetitions (the first is not counted)
-    const int reps = probe_steps >= 256 ? 3 : 7;
+    // short trials are noisier: more repetitions (the first is not counted;
+    // a 20-step call of 1M vehicles varies by a few per cent between calls,
+    // about the difference between the two fused forms)
+    const int reps = probe_steps >= 256 ? 3 : probe_steps >= 64 ? 7 : 15;
     ag_exec best = h->exec;
     float best_ms = 1e30f;
     const long long saved_t = h->t;
