@@ -525,6 +525,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             auto run = [&](auto ms) {
                 constexpr int MS = decltype(ms)::value;
                 for (int st = 0; st < s_ask; ++st) step<NR, false, false, false, MS>(s, C, P, gt, a.dt, a.g, nullptr, nullptr);
+                // each ticket goes to one wavefront, and a wavefront stops
+                // only at its first ticket past the queue's end, so every
+                // tile of the queue is taken
                 const unsigned k = ticket();
                 __builtin_amdgcn_s_waitcnt(kWaitVm0);
                 t_nxt = r0 + waves + (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)k);
