@@ -438,6 +438,7 @@ struct LaunchShape {
     dim3 grid, block;
     size_t shmem;
     int span;
+    bool ev_stage;       // the LDS holds a copy of each wavefront's reset events
 };
 
 // Launch shape of the work-queue kernel (exec kind 2).
@@ -469,6 +470,7 @@ std::string queue_shape(ag_handle h, const ag_exec& e, LaunchShape& s) {
     s.grid = dim3((unsigned)std::max(grid, nq));
     s.block = dim3(64);
     s.span = 1;
+    s.ev_stage = false;
     return "";
 }
 
@@ -500,6 +502,12 @@ std::string shape_for(ag_handle h, const ag_exec& e, LaunchShape& s) {
     s.block = dim3((unsigned)e.block);
     s.span = span;
     s.shmem = lds_bytes(span);
+    // event-fed launches of one vehicle per lane also copy each wavefront's
+    // events into LDS when that fits 64 KiB with the group entries (the
+    // overflow variant launched after them gets the same shape)
+    const size_t staged = ev_stage_offset(span) * sizeof(float) + (size_t)(e.block / 64) * 16 * kEvStage * sizeof(float);
+    s.ev_stage = events && vpl == 1 && staged <= 65536;
+    if (s.ev_stage) s.shmem = staged;
     return "";
 }
 
@@ -520,6 +528,7 @@ ag_status run_direct(ag_handle h, const ag_exec& e, int n_steps, StepArgs a, boo
     std::string m = shape_for(h, e, s);
     if (!m.empty()) return set_err(h, AG_E_INVALID, m);
     a.span = s.span;
+    a.ev_stage = s.ev_stage ? 1 : 0;
     a.d_step = nullptr;
     a.perm = nullptr;
     if (uses_order(h, e, n_steps)) {
@@ -571,6 +580,7 @@ ag_status build_graph(ag_handle h, int n_steps, bool ordered, GraphEntry& ge) {
     AG_HIP(h, hipGraphCreate(&g, 0));
     StepArgs a = base_args(h);
     a.span = s.span;
+    a.ev_stage = s.ev_stage ? 1 : 0;
     a.d_step = h->d_step;
     const int k = h->exec.kind == 0 ? 1 : h->exec.k;
     hipGraphNode_t prev = nullptr, node = nullptr;

@@ -77,6 +77,7 @@ struct StepArgs {
     EvBufs ev;                 // reset events (RESET kernels)
     const int32_t* perm;       // [n] vehicle of each lane position (fused kernels), or null: identity
     unsigned* queue;           // [kQueueWords] tile queues of the work-queue kernel (zero between launches)
+    int32_t ev_stage;          // event-fed kernels: the launch's LDS holds the per-wavefront event copies
 };
 
 struct ResetArgs {

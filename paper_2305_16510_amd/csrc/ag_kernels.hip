@@ -108,6 +108,10 @@ constexpr bool spec_loops(bool one, int vpl, bool obs, bool trk, int rst) {
     return !one && vpl == 1 && !trk && ((rst == 0 && !obs) || rst == 2);
 }
 
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVm0 = 0x0F70;                // every vector memory access done
+constexpr int kWaitLgkm0 = 0xC07F;              // every LDS access done
+
 // The tiles of one block.  UNI (per-step kernels of a single-group launch):
 // the one group entry is loaded ahead of the state and written to LDS
 // without the group search and its extra barrier.
@@ -120,6 +124,9 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
     constexpr bool EV = RESET && !ONE;
     constexpr bool FB = !(EV && RST == 2);
     constexpr bool SPEC = spec_loops(ONE, VPL, OBS, TRK, RST);
+    // every event of the launch in the buffer, one vehicle per lane: each
+    // wavefront copies its events into LDS at tile start
+    constexpr bool STAGE = EV && RST == 2 && VPL == 1;
     const int B = blockDim.x;
     const long long TILE = (long long)B * VPL;
     const long long tbase = a.d_step ? (*a.d_step + a.t_off) : a.t0;
@@ -180,18 +187,39 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             for (int r = 0; r < 4; ++r) tg[v][r] = a.target[r * ld + il];
         }
         // fused launches with resets: this launch's reset events of each lane
-        // (bit mask over the k steps, first event index) and the first
-        // event's redrawn state, fetched now so that its use costs nothing
+        // (bit mask over the k steps, index of its first event)
         unsigned long long evb[VPL];
-        long long evo[VPL];
-        int evr[VPL];
+        int evn[VPL];          // the lane's next event (event indices are int32)
         if constexpr (EV) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
                 const long long il = act[v] ? idx[v] : a.n - 1;
                 evb[v] = act[v] ? a.ev.bits[il] : 0ull;
-                evo[v] = a.ev.off[il];
-                evr[v] = 0;
+                evn[v] = a.ev.off[il];
+            }
+        }
+        // The wavefront's events are consecutive in the event list (vehicle
+        // order): its first kEvStage are copied into LDS by direct
+        // global-to-LDS loads, so that a reset reads the redrawn state there
+        // instead of waiting on memory (about half of all wavefront-steps hold
+        // a reset at 1 % per step); later events are read from the buffer.
+        // The range ends at lane 63's events: in a ragged last tile that lane
+        // holds vehicle n - 1's offset, so the last vehicle's events are read
+        // from the buffer.
+        int e_lo = 0, n_st = 0;
+        float* evs = lds;
+        if (STAGE && a.ev_stage) {
+            e_lo = __builtin_amdgcn_readfirstlane(evn[0]);
+            const int e_end = __builtin_amdgcn_readlane(evn[0] + __builtin_popcountll(evb[0]), 63);
+            n_st = e_end - e_lo < kEvStage ? e_end - e_lo : kEvStage;
+            const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+            evs = lds + ev_stage_offset(a.span) + (size_t)w * 16 * kEvStage;
+            if (n_st > 0) {
+                const long long e = (long long)e_lo + (threadIdx.x & 63);
+                const long long ec = e < a.ev.cap ? e : a.ev.cap - 1;
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    __builtin_amdgcn_global_load_lds(a.ev.data + r * a.ev.cap + ec, evs + r * kEvStage, 4, 0, 0);
             }
         }
         int cnt = 1;
@@ -214,6 +242,7 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
             }
         }
 
+        if (STAGE && a.ev_stage) __builtin_amdgcn_s_waitcnt(kWaitVm0);   // the events are in LDS
         Wrench W[VPL];
         float u[VPL][RotorClass<NR>::NR];
         uint4 mw[VPL];
@@ -245,8 +274,15 @@ __device__ __forceinline__ void step_tiles(const StepArgs& a, float* lds, int* l
                     if (hit) {
                         float gx, gy, gz;
                         if constexpr (EV) {
-                            const long long e = evo[v] + evr[v]++;
-                            if (e < a.ev.cap) {
+                            const int e = evn[v]++;
+                            if (STAGE && e - e_lo < n_st) {
+                                const float* ls = evs + (e - e_lo);
+#pragma unroll
+                                for (int r = 0; r < 13; ++r) s[v][r] = ls[r * kEvStage];
+                                gx = ls[13 * kEvStage];
+                                gy = ls[14 * kEvStage];
+                                gz = ls[15 * kEvStage];
+                            } else if (e < a.ev.cap) {
                                 const float* ed = a.ev.data + e;
 #pragma unroll
                                 for (int r = 0; r < 13; ++r) s[v][r] = ed[r * a.ev.cap];
@@ -437,9 +473,6 @@ void k_step(StepArgs a) {
 // a queue to finish clears them for the next launch.
 constexpr int kQueueRows = 17;                  // floats per lane copied ahead
 constexpr int kLead = 3;                        // steps left in a tile when the next is asked for
-// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
-constexpr int kWaitVm0 = 0x0F70;                // every vector memory access done
-constexpr int kWaitLgkm0 = 0xC07F;              // every LDS access done
 
 template <int NR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_step_q(StepArgs a) {

@@ -58,6 +58,15 @@ constexpr int G_NR = 86;          // rotor count, as float
 // rows above: A^+ thrust / x-y moment / yaw coefficients, sin(pi/4), c_tau
 constexpr int G_Q_F = 87, G_Q_XY = 88, G_Q_Z = 89, G_Q_S = 90, G_Q_CT = 91;
 
+// Event-fed fused kernels (one vehicle per lane) copy up to kEvStage reset
+// events (16 floats each) of every wavefront into LDS at tile start, after
+// the tile's group entries and their offsets: that region starts at this
+// float offset (16-byte aligned).
+constexpr int kEvStage = 64;
+__host__ __device__ constexpr size_t ev_stage_offset(int span) {
+    return ((size_t)span * GSTRIDE + (size_t)span + 1 + 3) & ~(size_t)3;
+}
+
 // ---- per-vehicle parameter rows (vparams) ---------------------------------
 constexpr int VP_MASS = 0, VP_J = 1, VP_GAINS = 4, VP_ARM = 14, VP_UMAX = 15;
 

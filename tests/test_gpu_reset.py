@@ -101,6 +101,41 @@ def test_automatic_resets_equal_explicit_resets(policy):
     b.close()
 
 
+@pytest.mark.parametrize("block,obs", [(64, False), (256, False), (256, True)])
+def test_event_fed_launches_with_staged_events(block, obs):
+    """Fused launches whose events all fit the buffer (p = 0.014, k = 64: about
+    0.9 events per vehicle and launch) copy each wavefront's first 64 events
+    into LDS; a wavefront expects 57, so many hold more and read the rest from
+    the buffer.  Equal to explicit ag_reset + ag_step(1), goals included."""
+    need_gpu()
+    wl = mixed(20_011, 44)
+    wl.reset_prob = 0.014
+    goal_a = torch.zeros(3, wl.n)
+    goal_b = torch.zeros(3, wl.n)
+    kw = dict(collect_stats=True, outputs=True) if obs else {}
+    a = make_sim(wl, auto_reset=True, goal=goal_a, **kw)
+    a.set_exec(kind=1, block=block, vpl=1, k=64, use_graph=1)
+    a.step(64)
+    a.step(64)
+    a.step(7)
+    a.sync()
+    b = make_sim(wl, goal=goal_b)
+    b.set_exec(kind=0, block=256, use_graph=0)
+    n_resets = 0
+    for t in range(135):
+        _, idx = b.reset(step=t)
+        n_resets += len(idx)
+        b.step(1)
+    b.sync()
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.target, b.target)
+    assert torch.equal(a.goal, b.goal)
+    if obs:
+        assert a.stats()["n_resets"] == n_resets
+    a.close()
+    b.close()
+
+
 def test_automatic_resets_past_the_event_buffer():
     """Fused launches find their resets before the launch and hold one event
     per vehicle; with p = 0.3 and k = 64 most events of a launch lie past that
