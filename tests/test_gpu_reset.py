@@ -136,6 +136,33 @@ def test_event_fed_launches_with_staged_events(block, obs):
     b.close()
 
 
+@pytest.mark.parametrize("block", [512, 64])
+def test_event_fed_launches_with_many_groups_per_tile(block):
+    """512 groups of four vehicles: a block of 512 lanes stages 129 group
+    entries, and with them the event copies would pass 64 KiB, so that launch
+    reads every event from the buffer; blocks of 64 copy them.  Both equal
+    explicit ag_reset + ag_step(1)."""
+    need_gpu()
+    wl = mixed(2048, 45)
+    wl.groups = [workloads.Group(first=4 * g, count=4) for g in range(512)]
+    wl.reset_prob = 0.012
+    a = make_sim(wl, auto_reset=True)
+    a.set_exec(kind=1, block=block, vpl=1, k=64, use_graph=1)
+    a.step(64)
+    a.step(9)
+    a.sync()
+    b = make_sim(wl)
+    b.set_exec(kind=0, block=256, use_graph=0)
+    for t in range(73):
+        b.reset(step=t)
+        b.step(1)
+    b.sync()
+    assert torch.equal(a.state, b.state)
+    assert torch.equal(a.target, b.target)
+    a.close()
+    b.close()
+
+
 def test_automatic_resets_past_the_event_buffer():
     """Fused launches find their resets before the launch and hold one event
     per vehicle; with p = 0.3 and k = 64 most events of a launch lie past that
