@@ -56,7 +56,7 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # x 64 lanes / vehicles / steps) for 20-step and 512-step launches.  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "8ca7d0bd7b214d8b",
+    "src": "de8dc94d50e1d5f7",
     "per_step_bytes": 127001805.0,
     "fused": {1: {"bytes": 131977216.0, "valu_per_vstep": {20: 151.2, 512: 140.0}},
               2: {"bytes": 151706829.0, "valu_per_vstep": {20: 147.1, 512: 139.8}}},

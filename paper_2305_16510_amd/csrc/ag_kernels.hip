@@ -885,11 +885,11 @@ __global__ __launch_bounds__(kOrderBlock) void k_mode_order(OrderArgs a) {
 }
 
 // Exclusive scan of the per-block event counts in place and their total (one
-// block, fixed order, 64-bit: totals may exceed 2^31).  Each thread sums a
-// contiguous run of counts, one block-wide scan combines the runs, and each
-// thread writes its run's offsets.
+// block, 64-bit: totals may exceed 2^31).  Each thread sums a contiguous run
+// of counts, shuffles within each wavefront and the wavefront totals combine
+// the runs (one barrier), and each thread writes its run's offsets.
 __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
-    __shared__ long long buf[1024];
+    __shared__ long long wtot[1024 / 64];
     const int nblocks = (int)((a.n + kResetBlock - 1) / kResetBlock);
     const int per = (nblocks + 1023) / 1024;
     const int b0 = (int)threadIdx.x * per;
@@ -908,15 +908,19 @@ __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
     } else {
         for (int j = b0; j < b1; ++j) run += a.ev.block_counts[j];
     }
-    buf[threadIdx.x] = run;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const long long t = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
-        __syncthreads();
-        buf[threadIdx.x] += t;
-        __syncthreads();
+    // inclusive sums of the runs: by shuffles within each wavefront, then
+    // the totals of the wavefronts before it (integer sums: exact in any order)
+    const int lane = (int)threadIdx.x & 63, wid = (int)threadIdx.x >> 6;
+    long long inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
     }
-    long long off = buf[threadIdx.x] - run;
+    if (lane == 63) wtot[wid] = inc;
+    __syncthreads();
+    for (int w = 0; w < wid; ++w) inc += wtot[w];
+    long long off = inc - run;
     if (per <= RUN) {
 #pragma unroll
         for (int j = 0; j < RUN; ++j) {
@@ -930,7 +934,7 @@ __global__ __launch_bounds__(1024) void k_ev_scan(StepArgs a) {
             off += c;
         }
     }
-    if (threadIdx.x == 1023) *a.ev.total = buf[1023];
+    if (threadIdx.x == 1023) *a.ev.total = inc;
 }
 
 // Per-vehicle first-event index (clamped to cap: events past cap are redrawn
