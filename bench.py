@@ -56,7 +56,7 @@ FP32_PEAK_TFLOPS = 157.3         # MI355X published FP32 vector peak
 # x 64 lanes / vehicles / steps) for 20-step and 512-step launches.  Valid
 # only while the step-kernel sources hash to ``src``.
 COUNTERS = {
-    "src": "de8dc94d50e1d5f7",
+    "src": "3b6bb056554e2e7b",
     "per_step_bytes": 127001805.0,
     "fused": {1: {"bytes": 131977216.0, "valu_per_vstep": {20: 151.2, 512: 140.0}},
               2: {"bytes": 151706829.0, "valu_per_vstep": {20: 147.1, 512: 139.8}}},
@@ -91,7 +91,7 @@ ROLLOUT_COUNTERS = {
 }
 ROLLOUT_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_rollout.hip",
                    "paper_2305_16510_amd/csrc/ag_internal.h")
-ROLLOUT_SRC = "863493a9662ec5db"
+ROLLOUT_SRC = "d7f2827642ee4154"
 STEP_SOURCES = ("paper_2305_16510_amd/csrc/ag_step.h", "paper_2305_16510_amd/csrc/ag_kernels.hip",
                 "paper_2305_16510_amd/csrc/ag_internal.h")
 PAPER_VSTEPS = 3.8e6             # Sec. VI: 2^17 robots, attitude/velocity commands, RTX 3090

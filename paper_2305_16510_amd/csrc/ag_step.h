@@ -818,13 +818,17 @@ constexpr uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u;
 constexpr uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u;
 constexpr uint32_t TAG_MASK = 0x4D41534Bu, TAG_DRAW = 0x44520000u;
 
+// a ^ b ^ c in one instruction (gfx950's three-input bitwise operation;
+// 0x96 is the truth table of the three-way exclusive or)
+AG_DEV uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+
 AG_DEV uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)PHILOX_M0 * c.x;
         const uint64_t p1 = (uint64_t)PHILOX_M1 * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1,
+                       xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0);
         k0 += PHILOX_W0;
         k1 += PHILOX_W1;
     }
